@@ -1,0 +1,203 @@
+/*
+ * hpmc.h -- C-ABI of the MI355X implicit-depletant hard-particle Monte Carlo
+ * library (libhpmc.so).
+ *
+ * Method: J. Glaser, A. S. Karas, S. C. Glotzer, "A parallel algorithm for
+ * implicit depletant simulations" (arXiv:1508.07077).  A sweep samples the
+ * semigrand ensemble exp(z_p V_f - beta H_cc) (Sec. III.A, Eq. gc_ensemble) of N
+ * hard colloids in a periodic cubic box with ideal penetrable depletants of
+ * diameter d_dep and fugacity z_p:
+ *   - trial moves on a shifted checkerboard of cells, 8 colours in random
+ *     order, particles confined to their cell (Sec. III.E);
+ *   - per move, a Poisson number of depletants uniform in the circumsphere of
+ *     the moved colloid (Sec. III.B step 2, Sec. III.C);
+ *   - rejection when a depletant free in the old configuration overlaps the
+ *     moved colloid (Sec. III.B step 3, Eq. pacc, Fig. 2);
+ *   - configurational-bias re-insertion for n_trial > 0 (Sec. III.D,
+ *     Eq. pacc_cb, multiple-try reading).
+ *
+ * Conventions
+ *   - Every function returns HPMC_OK (0) or a negative HPMC_E* code; nothing
+ *     aborts.  hpmc_last_error() returns a message for the last failure.
+ *   - Pointers documented "device" are HIP device allocations owned by the
+ *     caller; the library owns no device memory.  "host" pointers are read or
+ *     written synchronously.
+ *   - All device work is enqueued on the stream given to hpmc_create (NULL =
+ *     the default stream).  A handle is not thread-safe; handles are
+ *     independent of each other.
+ *   - Positions are SoA [3][n] doubles (x row, y row, z row) in [0, L];
+ *     orientations are SoA [4][n] unit quaternions (w, x, y, z rows).
+ */
+#ifndef HPMC_H
+#define HPMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes */
+#define HPMC_OK 0
+#define HPMC_EINVAL (-1)    /* invalid argument */
+#define HPMC_EBOX (-2)      /* box holds fewer than 2 cells of width 2 R_circ + d_dep per axis */
+#define HPMC_EOVERLAP (-3)  /* the state has overlapping colloids */
+#define HPMC_ENOMEM (-4)    /* workspace missing or too small */
+#define HPMC_ESTATE (-5)    /* called out of order (shape / state / workspace not set) */
+#define HPMC_EHIP (-6)      /* a HIP runtime call failed; see hpmc_last_error */
+#define HPMC_ECAPACITY (-7) /* a device-side capacity was exceeded during a sweep */
+
+/* shapes (hpmc_set_shape) */
+#define HPMC_SPHERE 0     /* params {d} */
+#define HPMC_HEMISPHERE 1 /* params {d}: half of a ball of diameter d; reference point = face centre,
+                             dome toward the body +z axis (Sec. V.A) */
+#define HPMC_DISCOID 2    /* params {a, r_s}: disk of radius a in the body xy plane swept by a ball of
+                             radius r_s */
+
+/* precision (hpmc_create) */
+#define HPMC_FP64 0          /* all geometry in FP64 */
+#define HPMC_FP32_GUARDED 1  /* FP32 depletant geometry, FP64 recomputation inside a guard band */
+
+/* trial outcomes (hpmc_move_record.reason) */
+#define HPMC_ACCEPT 0
+#define HPMC_REJ_CELL_EXIT 1
+#define HPMC_REJ_OVERLAP 2
+#define HPMC_REJ_DEPLETANT 3
+#define HPMC_REJ_CB_ZERO 4
+#define HPMC_REJ_CB_METROPOLIS 5
+
+/* observables (hpmc_observables) */
+#define HPMC_OBS_GR 0
+#define HPMC_OBS_FREE_VOLUME 1
+#define HPMC_OBS_SDF 2
+
+typedef struct hpmc_sim hpmc_sim;
+
+/* Counters accumulated over one hpmc_sweep call. */
+typedef struct hpmc_counters {
+    uint64_t trials;              /* trial moves (a particle was selected) */
+    uint64_t accepts;
+    uint64_t rej_cell_exit;
+    uint64_t rej_overlap;
+    uint64_t rej_depletant;
+    uint64_t rej_cb_zero;
+    uint64_t rej_cb_metropolis;
+    uint64_t depletants_drawn;    /* sum of N_p over trials that drew depletants */
+    uint64_t depletants_resolved; /* depletant checks in serial order up to each decision, + CB insertions */
+    uint64_t cb_trials;           /* CB trial insertions performed (serial semantics) */
+    uint64_t overlap_checks;      /* narrow-phase colloid-pair tests executed (implementation-specific) */
+    uint64_t near_contact;        /* colloid pairs decided within 1e-9 of contact */
+    uint64_t fp64_fallbacks;      /* FP64 recomputations of guarded FP32 decisions */
+    double phase_kernel_ms;       /* summed device time of the 8 phase launches of every sweep, from HIP
+                                     events recorded on the handle's stream around them */
+    double sweep_ms;              /* device time from the first to the last kernel of the call */
+} hpmc_counters;
+
+/* One record per trial, in cell order: index n_select * (first sorted slot of
+ * the cell) + t. */
+typedef struct hpmc_move_record {
+    uint32_t sweep;        /* low 32 bits of the sweep index */
+    uint32_t cell;         /* cell id cx + n (cy + n cz) */
+    uint32_t t;            /* round within the cell */
+    uint32_t particle;     /* selected particle */
+    uint32_t n_depletants; /* Poisson number drawn (0 if the trial ended before) */
+    uint32_t resolved;     /* depletant checks resolved in serial order, + CB insertions */
+    uint32_t n_blocking;   /* blocking depletants processed */
+    uint32_t w_fwd;        /* sum of forward CB weights W'_k */
+    uint32_t w_rev;        /* sum of reverse CB weights W_k */
+    uint8_t phase;         /* 0..7 */
+    uint8_t reason;        /* HPMC_ACCEPT or HPMC_REJ_* */
+    uint8_t rotation;      /* 1 if the proposal was a rotation */
+    uint8_t near_contact;  /* a colloid pair of this trial was decided within 1e-9 of contact */
+} hpmc_move_record;
+
+typedef struct hpmc_obs_params {
+    int32_t n_bins;   /* GR and SDF histogram bins */
+    int32_t n_fit;    /* SDF: leading bins of the linear extrapolation to zero compression */
+    double r_max;     /* GR: upper edge, <= L/2 */
+    double x_max;     /* SDF: upper edge of the compression histogram, in (0, 1) */
+    int64_t n_probe;  /* FREE_VOLUME and the SDF depletant term: uniform probes */
+    uint32_t obs_seq; /* selects the probe stream */
+    uint32_t pad;
+    double eps;       /* SDF depletant term: relative virtual expansion */
+} hpmc_obs_params;
+
+/* Create a handle for n colloids in a cubic periodic box of side box_L.
+ * seed and replica_id key the counter-based random streams (Philox4x32-10);
+ * precision is HPMC_FP64 or HPMC_FP32_GUARDED; hip_stream is a hipStream_t or
+ * NULL.  Allocates host metadata only.  Errors: EINVAL. */
+int hpmc_create(hpmc_sim** out, int64_t n, double box_L, uint64_t seed, uint32_t replica_id, int precision,
+                void* hip_stream);
+
+/* Release the handle (device buffers stay with the caller). */
+void hpmc_destroy(hpmc_sim* sim);
+
+/* Message of the last failure on this handle (valid until the next call). */
+const char* hpmc_last_error(const hpmc_sim* sim);
+
+/* Colloid shape (Sec. V: spheres, hemispheres, discoids).  params as listed at
+ * HPMC_SPHERE / HPMC_HEMISPHERE / HPMC_DISCOID.  Errors: EINVAL, EBOX. */
+int hpmc_set_shape(hpmc_sim* sim, int kind, const double* params, int nparams);
+
+/* Depletants (Sec. III.A, III.D): z_p is the depletant fugacity (reservoir
+ * number density, phi_p^r = (pi/6) d_dep^3 z_p); z_p = 0 disables them.
+ * n_trial = 0 is the plain scheme of Sec. III.B/C; n_trial in 1..255 enables
+ * configurational bias.  Errors: EINVAL, EBOX. */
+int hpmc_set_fugacity(hpmc_sim* sim, double z_p, double d_dep, int n_trial);
+
+/* Proposals (Sec. III.B step 1; symmetric): translation uniform in the cube
+ * [-d_trans, d_trans]^3 or, with probability p_rot (oriented shapes only),
+ * rotation q' = (q + a_rot v)/|q + a_rot v| with v uniform in the unit 4-ball.
+ * n_select trials per cell member and sweep.  Errors: EINVAL. */
+int hpmc_set_moves(hpmc_sim* sim, double d_trans, double a_rot, double p_rot, int n_select);
+
+/* Bytes of device workspace this handle needs with the current shape,
+ * fugacity, moves and trace setting. */
+int hpmc_workspace_bytes(const hpmc_sim* sim, size_t* bytes);
+
+/* Hand the library a device workspace of at least hpmc_workspace_bytes bytes
+ * (kept until replaced; the caller frees it after hpmc_destroy).  Errors:
+ * ENOMEM if too small, EINVAL if NULL. */
+int hpmc_set_workspace(hpmc_sim* sim, void* dev_ptr, size_t bytes);
+
+/* Borrow the caller's device state: pos_soa [3][n] doubles, quat_soa [4][n]
+ * doubles (required for oriented shapes, ignored for spheres), both kept for
+ * the lifetime of the handle; sweeps update them in place.  sweep_index sets
+ * the sweep counter of the random streams.  Synchronises the stream and checks
+ * that no two colloids overlap.  Errors: EINVAL, ESTATE, EOVERLAP, EHIP. */
+int hpmc_set_state(hpmc_sim* sim, double* pos_soa, double* quat_soa, uint64_t sweep_index);
+
+/* Current sweep index (the state itself is in the caller's buffers). */
+int hpmc_get_state(const hpmc_sim* sim, uint64_t* sweep_index);
+
+/* Record one hpmc_move_record per trial of the most recent sweep (parity
+ * mode).  Enabling it grows hpmc_workspace_bytes; device calls return ENOMEM
+ * until a large enough workspace is set.  Errors: EINVAL. */
+int hpmc_set_trace(hpmc_sim* sim, int enable);
+
+/* Run n_sweeps sweeps, enqueued on the stream.  If out is non-NULL the call
+ * synchronises and fills the counters summed over these sweeps (host).
+ * Errors: ESTATE, ENOMEM, EHIP, ECAPACITY (checked when out is non-NULL). */
+int hpmc_sweep(hpmc_sim* sim, int n_sweeps, hpmc_counters* out);
+
+/* Observables of the current state (host out, synchronous):
+ *   HPMC_OBS_GR: out[0..n_bins) = g(r) of reference-point distances on
+ *     [0, r_max), minimum image;
+ *   HPMC_OBS_FREE_VOLUME: out[0] = free-volume fraction alpha (probes that
+ *     overlap no colloid), out[1] = phi_p = phi_p^r alpha (Sec. IV.A),
+ *     out[2] = number of free probes;
+ *   HPMC_OBS_SDF: out[0] = beta P total, out[1] = rho (1 + s(0+)/6),
+ *     out[2] = z_p dV_f/dV (virtual expansion of the probe set), out[3] = s(0+),
+ *     out[4..4+n_bins) = s(x) histogram of the per-particle minimum compression.
+ * Errors: EINVAL, ESTATE, ENOMEM, EHIP. */
+int hpmc_observables(hpmc_sim* sim, int kind, const hpmc_obs_params* params, double* out, int64_t out_len);
+
+/* Copy the trace of the most recent sweep (host buf, cap records); requires
+ * hpmc_set_trace(sim, 1) before that sweep.  Errors: ESTATE, EHIP. */
+int hpmc_trace(hpmc_sim* sim, hpmc_move_record* buf, int64_t cap, int64_t* n_written);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1047,7 +1047,17 @@ int orc_try_move_many(orc_sim* s, int64_t j, const double* xnew, const double* q
 /* ------------------------------------------------------------------------ */
 /* Sweep (Sec. III.E): shifted checkerboard, 8 colours in random order.       */
 /* ------------------------------------------------------------------------ */
-static void sweep_once(orc_sim* s, orc_counters* cnt)
+static int cheb(int a, int b, int n)
+{
+    int d = a > b ? a - b : b - a;
+    return d < n - d ? d : n - d;
+}
+
+/* One sweep.  target < 0: every cell.  target >= 0: only the cells whose
+ * outcome can reach that cell's trials -- in phase q, the cells within
+ * (periodic Chebyshev) distance p* - q of it, p* being its own phase -- so a
+ * single cell of a large box is reproduced exactly without the whole sweep. */
+static void sweep_once(orc_sim* s, orc_counters* cnt, int64_t target)
 {
     int n = s->n;
     uint32_t sw = (uint32_t)s->sweep;
@@ -1105,12 +1115,26 @@ static void sweep_once(orc_sim* s, orc_counters* cnt)
         offs[2] = 1;
         noff = 3;
     }
+    int tx = 0, ty = 0, tz = 0, tphase = 7;
+    if (target >= 0) {
+        tx = (int)(target % n);
+        ty = (int)((target / n) % n);
+        tz = (int)(target / ((int64_t)n * n));
+        int tcol = (tx & 1) | ((ty & 1) << 1) | ((tz & 1) << 2);
+        for (int p = 0; p < 8; ++p)
+            if (perm[p] == tcol) tphase = p;
+    }
     for (int p = 0; p < 8; ++p) {
         int col = perm[p];
+        if (target >= 0 && p > tphase) break;
         for (int64_t c = 0; c < nc; ++c) {
             int cx = (int)(c % n), cy = (int)((c / n) % n), cz = (int)(c / ((int64_t)n * n));
             int ccol = (cx & 1) | ((cy & 1) << 1) | ((cz & 1) << 2);
             if (ccol != col) continue;
+            if (target >= 0) {
+                int reach = tphase - p;
+                if (cheb(cx, tx, n) > reach || cheb(cy, ty, n) > reach || cheb(cz, tz, n) > reach) continue;
+            }
             int nmem = s->cell_start[c + 1] - s->cell_start[c];
             if (nmem == 0) continue;
             int ntr = s->n_select * nmem;
@@ -1176,7 +1200,22 @@ int orc_sweep(orc_sim* s, int n_sweeps, orc_counters* out)
         free(s->trace);
         s->trace = (orc_record*)calloc((size_t)s->N * (size_t)s->n_select, sizeof(orc_record));
     }
-    for (int i = 0; i < n_sweeps; ++i) sweep_once(s, &c);
+    for (int i = 0; i < n_sweeps; ++i) sweep_once(s, &c, -1);
+    if (out) *out = c;
+    return 0;
+}
+
+int orc_sweep_cone(orc_sim* s, int64_t target_cell, orc_counters* out)
+{
+    if (!s->have_shape || !s->have_state) return fail(s, -5, "shape or state not set");
+    if (target_cell < 0 || target_cell >= s->ncells) return fail(s, -1, "target cell out of range");
+    orc_counters c;
+    memset(&c, 0, sizeof(c));
+    if (s->trace_on) {
+        free(s->trace);
+        s->trace = (orc_record*)calloc((size_t)s->N * (size_t)s->n_select, sizeof(orc_record));
+    }
+    sweep_once(s, &c, target_cell);
     if (out) *out = c;
     return 0;
 }

@@ -100,6 +100,7 @@ int orc_set_state(orc_sim* s, const double* pos_soa, const double* quat_soa, uin
 int orc_get_state(const orc_sim* s, double* pos_soa, double* quat_soa, uint64_t* sweep_index);
 int orc_set_trace(orc_sim* s, int enable);
 int orc_sweep(orc_sim* s, int n_sweeps, orc_counters* out);
+int orc_sweep_cone(orc_sim* s, int64_t target_cell, orc_counters* out);
 int orc_trace(const orc_sim* s, orc_record* buf, int64_t cap, int64_t* n_written);
 int orc_observables(orc_sim* s, int kind, const orc_obs_params* p, double* out, int64_t out_len);
 int orc_count_overlaps(orc_sim* s, int64_t* n_pairs);

@@ -108,6 +108,7 @@ def lib():
         L.orc_get_state.argtypes = [ctypes.c_void_p, c_d_p, c_d_p, ctypes.POINTER(ctypes.c_uint64)]
         L.orc_set_trace.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.orc_sweep.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(_Counters)]
+        L.orc_sweep_cone.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(_Counters)]
         L.orc_trace.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
         L.orc_observables.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(_ObsParams), c_d_p, ctypes.c_int64]
         L.orc_count_overlaps.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]
@@ -229,6 +230,12 @@ class OracleSim:
     def sweep(self, n_sweeps: int = 1) -> dict:
         c = _Counters()
         self._chk(lib().orc_sweep(self._h, int(n_sweeps), ctypes.byref(c)))
+        return {f: int(getattr(c, f)) for f in COUNTER_FIELDS}
+
+    def sweep_cone(self, target_cell: int) -> dict:
+        """One sweep restricted to the cells that can influence `target_cell`."""
+        c = _Counters()
+        self._chk(lib().orc_sweep_cone(self._h, int(target_cell), ctypes.byref(c)))
         return {f: int(getattr(c, f)) for f in COUNTER_FIELDS}
 
     def trace(self) -> np.ndarray:

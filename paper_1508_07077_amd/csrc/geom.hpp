@@ -1,0 +1,278 @@
+// geom.hpp -- shape predicates on the device (FP64, IEEE operations in a fixed
+// order; compiled without floating-point contraction).
+//
+// The paper (arXiv:1508.07077) uses hard spheres (Sec. IV), hemispheres
+// (Sec. V.A) and discoids (Sec. V.B) with penetrable spherical depletants but
+// gives no overlap algorithm.  Depletant-colloid tests here are exact distance
+// tests; colloid-colloid tests of convex shapes use Minkowski portal refinement
+// (MPR, "XenoCollide", G. Snethen, Game Programming Gems 7, 2008) on support
+// functions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+namespace hpmc {
+
+enum ShapeKind : int { kSphere = 0, kHemisphere = 1, kDiscoid = 2 };
+
+struct Vec3 {
+    double x, y, z;
+};
+
+__host__ __device__ inline Vec3 v3(double x, double y, double z) { return Vec3{x, y, z}; }
+__host__ __device__ inline Vec3 operator-(Vec3 a, Vec3 b) { return v3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__host__ __device__ inline Vec3 operator+(Vec3 a, Vec3 b) { return v3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__host__ __device__ inline Vec3 operator*(double s, Vec3 a) { return v3(s * a.x, s * a.y, s * a.z); }
+__host__ __device__ inline Vec3 neg(Vec3 a) { return v3(-a.x, -a.y, -a.z); }
+__host__ __device__ inline double dot(Vec3 a, Vec3 b) { return (a.x * b.x + a.y * b.y) + a.z * b.z; }
+__host__ __device__ inline Vec3 cross(Vec3 a, Vec3 b)
+{
+    return v3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+
+// body -> world rotation of the unit quaternion (w, x, y, z)
+struct Mat3 {
+    double m[9];
+};
+
+__host__ __device__ inline Mat3 quat_to_mat(double w, double x, double y, double z)
+{
+    double xx = x * x, yy = y * y, zz = z * z;
+    double xy = x * y, xz = x * z, yz = y * z;
+    double wx = w * x, wy = w * y, wz = w * z;
+    Mat3 R;
+    R.m[0] = 1.0 - 2.0 * (yy + zz);
+    R.m[1] = 2.0 * (xy - wz);
+    R.m[2] = 2.0 * (xz + wy);
+    R.m[3] = 2.0 * (xy + wz);
+    R.m[4] = 1.0 - 2.0 * (xx + zz);
+    R.m[5] = 2.0 * (yz - wx);
+    R.m[6] = 2.0 * (xz - wy);
+    R.m[7] = 2.0 * (yz + wx);
+    R.m[8] = 1.0 - 2.0 * (xx + yy);
+    return R;
+}
+
+// R^T v
+__host__ __device__ inline Vec3 to_body(const Mat3& R, Vec3 v)
+{
+    return v3((R.m[0] * v.x + R.m[3] * v.y) + R.m[6] * v.z, (R.m[1] * v.x + R.m[4] * v.y) + R.m[7] * v.z,
+              (R.m[2] * v.x + R.m[5] * v.y) + R.m[8] * v.z);
+}
+
+// R b
+__host__ __device__ inline Vec3 to_world(const Mat3& R, Vec3 b)
+{
+    return v3((R.m[0] * b.x + R.m[1] * b.y) + R.m[2] * b.z, (R.m[3] * b.x + R.m[4] * b.y) + R.m[5] * b.z,
+              (R.m[6] * b.x + R.m[7] * b.y) + R.m[8] * b.z);
+}
+
+// per-state-point shape constants (host-computed)
+struct Shape {
+    int kind;
+    int oriented;
+    double a;        // hemisphere radius d/2; discoid disk radius
+    double rs;       // discoid sweep radius
+    double rcirc;    // circumradius about the reference point
+    double dsq;      // sphere: d^2
+    double r_dep;    // depletant radius
+    double R0sq;     // (rcirc + r_dep)^2 : sphere and hemisphere dome threshold
+    double asq;      // a^2
+    double rdsq;     // r_dep^2
+    double rsd_sq;   // (r_s + r_dep)^2
+    double lim_sq;   // (2 rcirc)^2 : colloid circumsphere pre-test
+};
+
+// depletant of radius r_dep at body-frame point p overlaps the shape (strict)
+__host__ __device__ inline bool dep_overlap_body(const Shape& S, Vec3 p)
+{
+    double rho2 = p.x * p.x + p.y * p.y;
+    if (S.kind == kHemisphere) {
+        if (p.z >= 0.0) return rho2 + p.z * p.z < S.R0sq;
+        if (rho2 <= S.asq) return -p.z < S.r_dep;
+        double t = sqrt(rho2) - S.a;
+        return t * t + p.z * p.z < S.rdsq;
+    }
+    // discoid
+    if (rho2 <= S.asq) return p.z * p.z < S.rsd_sq;
+    double t = sqrt(rho2) - S.a;
+    return t * t + p.z * p.z < S.rsd_sq;
+}
+
+__host__ __device__ inline bool dep_overlap_sphere(const Shape& S, Vec3 v) { return dot(v, v) < S.R0sq; }
+
+__host__ __device__ inline bool dep_overlap(const Shape& S, Vec3 v, const Mat3& R)
+{
+    if (S.kind == kSphere) return dep_overlap_sphere(S, v);
+    return dep_overlap_body(S, to_body(R, v));
+}
+
+// ---------------------------------------------------------------------------
+// Support functions of the full shapes (body frame), direction n != 0.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline Vec3 support_body(const Shape& S, Vec3 n)
+{
+    double rho = sqrt(n.x * n.x + n.y * n.y);
+    if (S.kind == kHemisphere) {
+        if (n.z > 0.0) {
+            double inv = S.a / sqrt(dot(n, n));
+            return v3(n.x * inv, n.y * inv, n.z * inv);
+        }
+        if (rho > 0.0) return v3(S.a * n.x / rho, S.a * n.y / rho, 0.0);
+        return v3(0.0, 0.0, 0.0);
+    }
+    // discoid: disk support + ball support
+    double nn = sqrt(dot(n, n));
+    Vec3 s = v3(S.rs * n.x / nn, S.rs * n.y / nn, S.rs * n.z / nn);
+    if (rho > 0.0) {
+        s.x = s.x + S.a * n.x / rho;
+        s.y = s.y + S.a * n.y / rho;
+    }
+    return s;
+}
+
+__host__ __device__ inline Vec3 support_world(const Shape& S, const Mat3& R, Vec3 c, Vec3 n)
+{
+    return c + to_world(R, support_body(S, to_body(R, n)));
+}
+
+struct PairResult {
+    bool overlap;
+    bool near;
+};
+
+// Minkowski portal refinement on the difference B - A (B at offset d with
+// rotation RB, A at the origin with rotation RA).  The origin lies inside the
+// difference iff the shapes overlap.  Interior seed: difference of the
+// shapes' interior points (hemisphere centroid (0,0,3a/8), disk centre).
+__host__ __device__ inline PairResult mpr_overlap(const Shape& S, Vec3 d, const Mat3& RA, const Mat3& RB)
+{
+    const double tol = 1e-13;
+    PairResult res{false, false};
+    Vec3 cin = v3(0.0, 0.0, S.kind == kHemisphere ? 0.375 * S.a : 0.0);
+    Vec3 zero = v3(0.0, 0.0, 0.0);
+    Vec3 v0 = (d + to_world(RB, cin)) - to_world(RA, cin);
+    if (dot(v0, v0) < 1e-30) v0 = v3(1e-12, 0.0, 0.0);
+    // support of B - A in direction n
+#define HPMC_SUP(n) (support_world(S, RB, d, (n)) - support_world(S, RA, zero, neg(n)))
+    Vec3 n = neg(v0);
+    Vec3 v1 = HPMC_SUP(n);
+    if (dot(v1, n) <= 0.0) return res;
+    n = cross(v1, v0);
+    if (dot(n, n) < 1e-30) {
+        res.overlap = true;
+        return res;
+    }
+    Vec3 v2 = HPMC_SUP(n);
+    if (dot(v2, n) <= 0.0) return res;
+    n = cross(v1 - v0, v2 - v0);
+    if (dot(n, v0) > 0.0) {
+        Vec3 t = v1;
+        v1 = v2;
+        v2 = t;
+        n = neg(n);
+    }
+    Vec3 v3p = v0;
+    // portal discovery: a triangle (v1, v2, v3) whose cone from v0 holds the origin ray
+    int it = 0;
+    for (; it < 64; ++it) {
+        v3p = HPMC_SUP(n);
+        if (dot(v3p, n) <= 0.0) return res;
+        if (dot(cross(v1, v3p), v0) < 0.0) {
+            v2 = v3p;
+            n = cross(v1 - v0, v3p - v0);
+            continue;
+        }
+        if (dot(cross(v3p, v2), v0) < 0.0) {
+            v1 = v3p;
+            n = cross(v3p - v0, v2 - v0);
+            continue;
+        }
+        break;
+    }
+    if (it == 64) {
+        res.near = true;
+        return res;
+    }
+    // portal refinement
+    for (int k = 0; k < 96; ++k) {
+        n = cross(v2 - v1, v3p - v1);
+        if (dot(n, v1) >= 0.0) {
+            res.overlap = true;
+            return res;
+        }
+        Vec3 v4 = HPMC_SUP(n);
+        double nn = sqrt(dot(n, n));
+        if (dot(v4, n) <= 0.0) {
+            res.near = (-dot(v4, n) < 1e-9 * nn);
+            return res;
+        }
+        if (dot(v4 - v3p, n) <= tol * nn || dot(v4 - v1, n) <= tol * nn || dot(v4 - v2, n) <= tol * nn) {
+            // support plane within tolerance of the portal: contact within rounding
+            res.near = true;
+            res.overlap = false;
+            return res;
+        }
+        Vec3 dd = cross(v4, v0);
+        if (dot(v1, dd) > 0.0) {
+            if (dot(v2, dd) > 0.0)
+                v1 = v4;
+            else
+                v3p = v4;
+        } else {
+            if (dot(v3p, dd) > 0.0)
+                v2 = v4;
+            else
+                v1 = v4;
+        }
+    }
+#undef HPMC_SUP
+    res.near = true;
+    return res;
+}
+
+// compile-time shape dispatch for the hot loops
+template <int KIND>
+__host__ __device__ inline bool dep_ov(const Shape& S, Vec3 v, const Mat3& R)
+{
+    if constexpr (KIND == kSphere) {
+        return dot(v, v) < S.R0sq;
+    } else {
+        Vec3 p = to_body(R, v);
+        double rho2 = p.x * p.x + p.y * p.y;
+        if constexpr (KIND == kHemisphere) {
+            if (p.z >= 0.0) return rho2 + p.z * p.z < S.R0sq;
+            if (rho2 <= S.asq) return -p.z < S.r_dep;
+            double t = sqrt(rho2) - S.a;
+            return t * t + p.z * p.z < S.rdsq;
+        } else {
+            if (rho2 <= S.asq) return p.z * p.z < S.rsd_sq;
+            double t = sqrt(rho2) - S.a;
+            return t * t + p.z * p.z < S.rsd_sq;
+        }
+    }
+}
+
+// colloid-colloid overlap: B at offset d from A
+__host__ __device__ inline PairResult pair_overlap(const Shape& S, Vec3 d, const Mat3& RA, const Mat3& RB)
+{
+    double dd = dot(d, d);
+    if (S.kind == kSphere) return PairResult{dd < S.dsq, false};
+    if (dd >= S.lim_sq) return PairResult{false, false};
+    return mpr_overlap(S, d, RA, RB);
+}
+
+template <int KIND>
+__host__ __device__ inline PairResult pair_ov(const Shape& S, Vec3 d, const Mat3& RA, const Mat3& RB)
+{
+    double dd = dot(d, d);
+    if constexpr (KIND == kSphere) {
+        return PairResult{dd < S.dsq, false};
+    } else {
+        if (dd >= S.lim_sq) return PairResult{false, false};
+        return mpr_overlap(S, d, RA, RB);
+    }
+}
+
+}  // namespace hpmc

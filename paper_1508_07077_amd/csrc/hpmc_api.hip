@@ -1,0 +1,622 @@
+// hpmc_api.hip -- C-ABI of the implicit-depletant hard-particle Monte Carlo
+// library (declared in include/hpmc.h).  Host-side validation, derived
+// parameters, workspace layout and the launch sequence of one sweep:
+//   grid shift + colour order, cell list (Sec. III.E)
+//   8 phase launches, one per colour in random order (Sec. III.E)
+//   scatter of the cell-ordered records back to the caller's SoA state
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "hpmc.h"
+#include "kernels.hpp"
+
+using namespace hpmc;
+
+struct hpmc_sim {
+    int64_t N = 0;
+    double L = 0, halfL = 0;
+    uint64_t seed = 0;
+    uint32_t replica = 0;
+    int precision = HPMC_FP64;
+    hipStream_t stream = nullptr;
+    // shape
+    int have_shape = 0;
+    int kind = 0;
+    double par[2] = {0, 0};
+    Shape S{};
+    double vol_p = 0;
+    // depletants and moves
+    double z_p = 0, d_dep = 0;
+    int n_trial = 0;
+    double d_trans = 0.1, a_rot = 0, p_rot = 0;
+    int n_select = 1;
+    // derived
+    int n = 0;
+    double w = 0, inv_w = 0, R0 = 0, lambda = 0, lambda_c = 0, s_ball = 0;
+    int n_chunks = 1;
+    double F[kPoissonK];
+    int F_dirty = 1;
+    // state and workspace
+    double* pos = nullptr;
+    double* quat = nullptr;
+    uint64_t sweep = 0;
+    int have_state = 0;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    Work W{};
+    int trace = 0;
+    int trace_valid = 0;
+    std::vector<hipEvent_t> events;  // timing of phase launches (counters requested)
+    std::string err;
+    ~hpmc_sim()
+    {
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+int fail(hpmc_sim* s, int code, const std::string& msg)
+{
+    if (s) s->err = msg;
+    return code;
+}
+
+int hip_fail(hpmc_sim* s, hipError_t e, const char* where)
+{
+    return fail(s, HPMC_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+// derived parameters, in the order of the determinism contract
+int derive(hpmc_sim* s)
+{
+    if (!s->have_shape) return HPMC_OK;
+    double rcirc = s->S.rcirc;
+    double r_dep = 0.5 * s->d_dep;
+    s->R0 = rcirc + r_dep;
+    double wmin = 2.0 * rcirc + s->d_dep;
+    int n = static_cast<int>(floor(s->L / wmin));
+    if (n % 2) n -= 1;
+    if (n < 2) return fail(s, HPMC_EBOX, "box smaller than two cells of width 2 R_circ + d_dep");
+    if (static_cast<int64_t>(n) * n * n > 0x3FFFFFFF) return fail(s, HPMC_EBOX, "too many cells");
+    s->n = n;
+    s->w = s->L / static_cast<double>(n);
+    s->inv_w = 1.0 / s->w;
+    s->s_ball = s->R0 * 0x1p-21;
+    double vol0 = 4.0 / 3.0 * M_PI * s->R0 * s->R0 * s->R0;
+    s->lambda = s->z_p * vol0;
+    int m = static_cast<int>(ceil(s->lambda / 256.0));
+    if (m < 1) m = 1;
+    s->n_chunks = m;
+    s->lambda_c = s->lambda / static_cast<double>(m);
+    double P = exp(-s->lambda_c);
+    s->F[0] = P;
+    for (int k = 1; k < kPoissonK - 1; ++k) {
+        P = P * (s->lambda_c / static_cast<double>(k));
+        s->F[k] = s->F[k - 1] + P;
+    }
+    s->F[kPoissonK - 1] = 2.0;
+    s->F_dirty = 1;
+    Shape& S = s->S;
+    S.r_dep = r_dep;
+    S.R0sq = s->R0 * s->R0;
+    S.rdsq = r_dep * r_dep;
+    S.rsd_sq = (S.rs + r_dep) * (S.rs + r_dep);
+    return HPMC_OK;
+}
+
+struct Layout {
+    size_t cell_count, cell_start, scan_tmp, pcell, prank, order, rpos, rquat, F, grid, perm, counters, flags, obs,
+        trace, total;
+};
+
+constexpr int kObsWords = 8192;
+
+Layout layout(const hpmc_sim* s)
+{
+    Layout l{};
+    size_t ncells = static_cast<size_t>(s->n) * s->n * s->n;
+    size_t N = static_cast<size_t>(s->N);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    l.cell_count = take(ncells * 4);
+    l.cell_start = take((ncells + 1) * 4);
+    l.scan_tmp = take(((ncells + 1023) / 1024 + 1) * 4);
+    l.pcell = take(N * 4);
+    l.prank = take(N * 4);
+    l.order = take(N * 4);
+    l.rpos = take(N * 32);
+    l.rquat = take(s->S.oriented ? N * 32 : 0);
+    l.F = take(kPoissonK * 8);
+    l.grid = take(4 * 8);
+    l.perm = take(8 * 4);
+    l.counters = take(static_cast<size_t>(kCounterCopies) * kCounterStride * 8);
+    l.flags = take(4 * 4);
+    l.obs = take(static_cast<size_t>(kObsWords) * 8);
+    l.trace = take(s->trace ? N * static_cast<size_t>(s->n_select) * sizeof(hpmc_move_record) : 0);
+    l.total = off;
+    return l;
+}
+
+void bind_work(hpmc_sim* s)
+{
+    Layout l = layout(s);
+    unsigned char* b = static_cast<unsigned char*>(s->ws);
+    Work& W = s->W;
+    W.cell_count = reinterpret_cast<int*>(b + l.cell_count);
+    W.cell_start = reinterpret_cast<int*>(b + l.cell_start);
+    W.scan_tmp = reinterpret_cast<int*>(b + l.scan_tmp);
+    W.pcell = reinterpret_cast<int*>(b + l.pcell);
+    W.prank = reinterpret_cast<int*>(b + l.prank);
+    W.order = reinterpret_cast<int*>(b + l.order);
+    W.rpos = reinterpret_cast<double4*>(b + l.rpos);
+    W.rquat = s->S.oriented ? reinterpret_cast<double4*>(b + l.rquat) : nullptr;
+    W.F = reinterpret_cast<double*>(b + l.F);
+    W.grid = reinterpret_cast<double*>(b + l.grid);
+    W.perm = reinterpret_cast<int*>(b + l.perm);
+    W.counters = reinterpret_cast<unsigned long long*>(b + l.counters);
+    W.flags = reinterpret_cast<int*>(b + l.flags);
+    W.obs = reinterpret_cast<unsigned long long*>(b + l.obs);
+    W.trace = s->trace ? static_cast<void*>(b + l.trace) : nullptr;
+}
+
+int64_t packing_bound(const hpmc_sim* s, double side)
+{
+    double v = side * side * side / s->vol_p;
+    if (v > 1e9) v = 1e9;
+    int64_t b = static_cast<int64_t>(floor(v)) + 1;
+    return std::min<int64_t>(b, s->N);
+}
+
+Params make_params(const hpmc_sim* s)
+{
+    Params P{};
+    P.S = s->S;
+    P.N = static_cast<int>(s->N);
+    P.n = s->n;
+    P.h = s->n / 2;
+    P.ncells = s->n * s->n * s->n;
+    P.active_cells = P.h * P.h * P.h;
+    P.n_select = s->n_select;
+    P.n_trial = s->n_trial;
+    P.n_chunks = s->n_chunks;
+    P.has_dep = s->z_p > 0.0 ? 1 : 0;
+    P.trace = s->trace;
+    P.precision = s->precision;
+    P.key0 = static_cast<uint32_t>(s->seed & 0xFFFFFFFFu);
+    P.key1 = static_cast<uint32_t>(s->seed >> 32) ^ s->replica;
+    P.sweep = static_cast<uint32_t>(s->sweep);
+    P.L = s->L;
+    P.halfL = s->halfL;
+    P.w = s->w;
+    P.inv_w = s->inv_w;
+    P.d_trans = s->d_trans;
+    P.a_rot = s->a_rot;
+    P.p_rot = s->S.oriented ? s->p_rot : 0.0;
+    P.s_ball = s->s_ball;
+    // per-wave LDS of the phase kernel: rigorous packing bounds (hard bodies
+    // are disjoint) for the stencil list and own-cell records
+    double rc2 = 2.0 * s->S.rcirc;
+    int64_t list_cap = (s->n == 2) ? s->N : packing_bound(s, 3.0 * s->w + rc2);
+    int64_t own_cap = (s->n == 2) ? s->N : packing_bound(s, s->w + rc2);
+    int gs = s->S.oriented ? 12 : 3;
+    int64_t geo_cap = s->S.oriented ? std::min<int64_t>(list_cap, 96) : std::min<int64_t>(list_cap, 512);
+    P.list_cap = static_cast<int>(list_cap);
+    P.own_cap = static_cast<int>(own_cap);
+    P.geo_cap = static_cast<int>(geo_cap);
+    size_t off = align256(static_cast<size_t>(list_cap) * 4);
+    P.off_own_pos = static_cast<int>(off);
+    off = align256(off + static_cast<size_t>(own_cap) * 32);
+    P.off_own_q = static_cast<int>(off);
+    if (s->S.oriented) off = align256(off + static_cast<size_t>(own_cap) * 32);
+    P.off_geo = static_cast<int>(off);
+    off = align256(off + static_cast<size_t>(geo_cap) * 8 * gs);
+    P.wave_lds = static_cast<int>(off);
+    int wpb = 4;
+    while (wpb > 1 && kPoissonK * 8 + static_cast<size_t>(wpb) * off > 64 * 1024) wpb >>= 1;
+    P.waves_per_block = wpb;
+    return P;
+}
+
+StateRef state_ref(const hpmc_sim* s) { return StateRef{s->pos, s->quat}; }
+
+int check_ready(hpmc_sim* s, bool need_state)
+{
+    if (!s->have_shape) return fail(s, HPMC_ESTATE, "shape not set");
+    if (!s->ws) return fail(s, HPMC_ESTATE, "workspace not set");
+    if (s->ws_bytes < layout(s).total) return fail(s, HPMC_ENOMEM, "workspace too small for the current settings");
+    if (need_state && !s->have_state) return fail(s, HPMC_ESTATE, "state not set");
+    Params P = make_params(s);
+    if (kPoissonK * 8 + static_cast<size_t>(P.waves_per_block) * P.wave_lds > 64 * 1024)
+        return fail(s, HPMC_ECAPACITY, "stencil too large for the LDS of one workgroup");
+    return HPMC_OK;
+}
+
+int upload_table(hpmc_sim* s)
+{
+    if (!s->F_dirty) return HPMC_OK;
+    hipError_t e = hipMemcpyAsync(s->W.F, s->F, sizeof(s->F), hipMemcpyHostToDevice, s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "hipMemcpyAsync(table)");
+    s->F_dirty = 0;
+    return HPMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hpmc_create(hpmc_sim** out, int64_t n, double box_L, uint64_t seed, uint32_t replica_id, int precision,
+                void* hip_stream)
+{
+    if (!out) return HPMC_EINVAL;
+    *out = nullptr;
+    if (n < 1 || n > 0x3FFFFFFF || !(box_L > 0.0) || !isfinite(box_L)) return HPMC_EINVAL;
+    if (precision != HPMC_FP64 && precision != HPMC_FP32_GUARDED) return HPMC_EINVAL;
+    hpmc_sim* s = new hpmc_sim();
+    s->N = n;
+    s->L = box_L;
+    s->halfL = 0.5 * box_L;
+    s->seed = seed;
+    s->replica = replica_id;
+    s->precision = precision;
+    s->stream = static_cast<hipStream_t>(hip_stream);
+    *out = s;
+    return HPMC_OK;
+}
+
+void hpmc_destroy(hpmc_sim* sim) { delete sim; }
+
+const char* hpmc_last_error(const hpmc_sim* sim) { return sim ? sim->err.c_str() : "null handle"; }
+
+int hpmc_set_shape(hpmc_sim* s, int kind, const double* p, int np)
+{
+    if (!s) return HPMC_EINVAL;
+    if (!p) return fail(s, HPMC_EINVAL, "null shape parameters");
+    Shape S{};
+    S.kind = kind;
+    double vol;
+    if (kind == HPMC_SPHERE || kind == HPMC_HEMISPHERE) {
+        if (np < 1 || !(p[0] > 0.0) || !isfinite(p[0])) return fail(s, HPMC_EINVAL, "diameter must be positive");
+        S.a = 0.5 * p[0];
+        S.rcirc = 0.5 * p[0];
+        S.dsq = p[0] * p[0];
+        S.oriented = kind == HPMC_HEMISPHERE;
+        vol = (kind == HPMC_SPHERE) ? M_PI * p[0] * p[0] * p[0] / 6.0 : M_PI * p[0] * p[0] * p[0] / 12.0;
+    } else if (kind == HPMC_DISCOID) {
+        if (np < 2 || !(p[0] > 0.0) || !(p[1] > 0.0)) return fail(s, HPMC_EINVAL, "disk and sweep radii must be positive");
+        S.a = p[0];
+        S.rs = p[1];
+        S.rcirc = p[0] + p[1];
+        S.dsq = 4.0 * S.rcirc * S.rcirc;
+        S.oriented = 1;
+        vol = 2.0 * M_PI * p[0] * p[0] * p[1] + M_PI * M_PI * p[0] * p[1] * p[1] + 4.0 / 3.0 * M_PI * p[1] * p[1] * p[1];
+    } else {
+        return fail(s, HPMC_EINVAL, "unknown shape");
+    }
+    S.asq = S.a * S.a;
+    S.lim_sq = (2.0 * S.rcirc) * (2.0 * S.rcirc);
+    hpmc_sim saved = *s;
+    s->S = S;
+    s->kind = kind;
+    s->par[0] = p[0];
+    s->par[1] = np > 1 ? p[1] : 0.0;
+    s->vol_p = vol;
+    s->have_shape = 1;
+    int r = derive(s);
+    if (r != HPMC_OK) {
+        std::string e = s->err;
+        *s = saved;
+        s->err = e;
+        return r;
+    }
+    if (s->ws) bind_work(s);
+    return HPMC_OK;
+}
+
+int hpmc_set_fugacity(hpmc_sim* s, double z_p, double d_dep, int n_trial)
+{
+    if (!s) return HPMC_EINVAL;
+    if (!(z_p >= 0.0) || !isfinite(z_p) || !(d_dep >= 0.0) || !isfinite(d_dep) || n_trial < 0 || n_trial > 255)
+        return fail(s, HPMC_EINVAL, "invalid depletant parameters");
+    double oz = s->z_p, od = s->d_dep;
+    int ot = s->n_trial;
+    s->z_p = z_p;
+    s->d_dep = d_dep;
+    s->n_trial = n_trial;
+    int r = derive(s);
+    if (r == HPMC_OK && s->lambda > 60000.0) r = fail(s, HPMC_EINVAL, "mean depletant number per move too large");
+    if (r != HPMC_OK) {
+        s->z_p = oz;
+        s->d_dep = od;
+        s->n_trial = ot;
+        derive(s);
+        return r;
+    }
+    if (s->ws) bind_work(s);
+    return HPMC_OK;
+}
+
+int hpmc_set_moves(hpmc_sim* s, double d_trans, double a_rot, double p_rot, int n_select)
+{
+    if (!s) return HPMC_EINVAL;
+    if (!(d_trans >= 0.0) || !isfinite(d_trans) || !(a_rot >= 0.0) || !isfinite(a_rot) || !(p_rot >= 0.0 && p_rot <= 1.0) ||
+        n_select < 1 || n_select > 1024)
+        return fail(s, HPMC_EINVAL, "invalid move parameters");
+    s->d_trans = d_trans;
+    s->a_rot = a_rot;
+    s->p_rot = p_rot;
+    s->n_select = n_select;
+    if (s->ws) bind_work(s);
+    return HPMC_OK;
+}
+
+int hpmc_workspace_bytes(const hpmc_sim* s, size_t* bytes)
+{
+    if (!s || !bytes) return HPMC_EINVAL;
+    if (!s->have_shape) return HPMC_ESTATE;
+    *bytes = layout(s).total;
+    return HPMC_OK;
+}
+
+int hpmc_set_workspace(hpmc_sim* s, void* dev_ptr, size_t bytes)
+{
+    if (!s) return HPMC_EINVAL;
+    if (!dev_ptr) return fail(s, HPMC_EINVAL, "null workspace");
+    if (!s->have_shape) return fail(s, HPMC_ESTATE, "shape not set");
+    if (bytes < layout(s).total) return fail(s, HPMC_ENOMEM, "workspace too small");
+    s->ws = dev_ptr;
+    s->ws_bytes = bytes;
+    s->F_dirty = 1;
+    bind_work(s);
+    return HPMC_OK;
+}
+
+int hpmc_set_trace(hpmc_sim* s, int enable)
+{
+    if (!s) return HPMC_EINVAL;
+    s->trace = enable ? 1 : 0;
+    s->trace_valid = 0;
+    // a larger workspace may now be needed; device calls refuse (ENOMEM) until it is set
+    if (s->ws && s->ws_bytes >= layout(s).total) bind_work(s);
+    return HPMC_OK;
+}
+
+int hpmc_set_state(hpmc_sim* s, double* pos, double* quat, uint64_t sweep_index)
+{
+    if (!s) return HPMC_EINVAL;
+    if (!pos) return fail(s, HPMC_EINVAL, "null positions");
+    if (s->have_shape && s->S.oriented && !quat) return fail(s, HPMC_EINVAL, "oriented shape needs quaternions");
+    int r = check_ready(s, false);
+    if (r != HPMC_OK) return r;
+    s->pos = pos;
+    s->quat = s->S.oriented ? quat : nullptr;
+    s->sweep = sweep_index;
+    s->have_state = 1;
+    s->trace_valid = 0;
+    // hard-core check on a cell list with zero shift
+    Params P = make_params(s);
+    hipError_t e = launch_build_cells(P, s->W, state_ref(s), false, s->stream);
+    if (e == hipSuccess) e = launch_fill_u64(s->W.obs, 1, s->stream);
+    if (e == hipSuccess) e = launch_overlap_count(P, s->W, s->stream);
+    unsigned long long cnt = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&cnt, s->W.obs, 8, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        s->have_state = 0;
+        return hip_fail(s, e, "set_state");
+    }
+    if (cnt > 0) {
+        s->have_state = 0;
+        return fail(s, HPMC_EOVERLAP, std::to_string(cnt) + " overlapping colloid pairs");
+    }
+    return HPMC_OK;
+}
+
+int hpmc_get_state(const hpmc_sim* s, uint64_t* sweep_index)
+{
+    if (!s || !sweep_index) return HPMC_EINVAL;
+    if (!s->have_state) return HPMC_ESTATE;
+    *sweep_index = s->sweep;
+    return HPMC_OK;
+}
+
+int hpmc_sweep(hpmc_sim* s, int n_sweeps, hpmc_counters* out)
+{
+    if (!s) return HPMC_EINVAL;
+    if (n_sweeps < 0) return fail(s, HPMC_EINVAL, "negative sweep count");
+    int r = check_ready(s, true);
+    if (r != HPMC_OK) return r;
+    r = upload_table(s);
+    if (r != HPMC_OK) return r;
+    hipError_t e = hipSuccess;
+    const bool timed = out != nullptr;
+    if (timed) {
+        size_t need = 2 * static_cast<size_t>(n_sweeps) + 2;
+        while (s->events.size() < need) {
+            hipEvent_t ev;
+            e = hipEventCreate(&ev);
+            if (e != hipSuccess) return hip_fail(s, e, "hipEventCreate");
+            s->events.push_back(ev);
+        }
+        e = hipEventRecord(s->events[0], s->stream);
+        if (e != hipSuccess) return hip_fail(s, e, "hipEventRecord");
+    }
+    e = launch_fill_u64(s->W.counters, kCounterCopies * kCounterStride, s->stream);
+    if (e == hipSuccess) e = launch_fill_int(s->W.flags, 4, 0, s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "sweep setup");
+    for (int i = 0; i < n_sweeps; ++i) {
+        Params P = make_params(s);
+        e = launch_build_cells(P, s->W, state_ref(s), true, s->stream);
+        if (e == hipSuccess && timed) e = hipEventRecord(s->events[2 + 2 * i], s->stream);
+        for (int p = 0; p < 8 && e == hipSuccess; ++p) e = launch_phase(P, s->W, p, s->stream);
+        if (e == hipSuccess && timed) e = hipEventRecord(s->events[3 + 2 * i], s->stream);
+        if (e == hipSuccess) e = launch_scatter_back(P, s->W, state_ref(s), s->stream);
+        if (e != hipSuccess) return hip_fail(s, e, "sweep launch");
+        s->sweep++;
+    }
+    s->trace_valid = s->trace && n_sweeps > 0;
+    if (out) {
+        unsigned long long host[kCounterStride];
+        int flags = 0;
+        e = launch_reduce_counters(s->W, s->stream);
+        if (e == hipSuccess) e = hipEventRecord(s->events[1], s->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(host, s->W.counters, sizeof(host), hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(&flags, s->W.flags, 4, hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return hip_fail(s, e, "sweep counters");
+        memset(out, 0, sizeof(*out));
+        uint64_t* o = reinterpret_cast<uint64_t*>(out);
+        for (int k = 0; k < kNumCounters; ++k) o[k] = host[k];
+        double phase_ms = 0.0;
+        for (int i = 0; i < n_sweeps; ++i) {
+            float ms = 0.0f;
+            e = hipEventElapsedTime(&ms, s->events[2 + 2 * i], s->events[3 + 2 * i]);
+            if (e != hipSuccess) return hip_fail(s, e, "hipEventElapsedTime");
+            phase_ms += ms;
+        }
+        float all = 0.0f;
+        e = hipEventElapsedTime(&all, s->events[0], s->events[1]);
+        if (e != hipSuccess) return hip_fail(s, e, "hipEventElapsedTime");
+        out->phase_kernel_ms = phase_ms;
+        out->sweep_ms = all;
+        if (flags) return fail(s, HPMC_ECAPACITY, "stencil or cell capacity exceeded (flags " + std::to_string(flags) + ")");
+    }
+    return HPMC_OK;
+}
+
+int hpmc_trace(hpmc_sim* s, hpmc_move_record* buf, int64_t cap, int64_t* n_written)
+{
+    if (!s || !n_written || (cap > 0 && !buf)) return HPMC_EINVAL;
+    *n_written = 0;
+    if (!s->trace || !s->trace_valid) return fail(s, HPMC_ESTATE, "no traced sweep");
+    int64_t n = s->N * s->n_select;
+    if (n > cap) n = cap;
+    if (n > 0) {
+        hipError_t e = hipMemcpyAsync(buf, s->W.trace, static_cast<size_t>(n) * sizeof(hpmc_move_record),
+                                      hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return hip_fail(s, e, "trace copy");
+    }
+    *n_written = n;
+    return HPMC_OK;
+}
+
+int hpmc_observables(hpmc_sim* s, int kind, const hpmc_obs_params* p, double* out, int64_t out_len)
+{
+    if (!s) return HPMC_EINVAL;
+    if (!p || !out) return fail(s, HPMC_EINVAL, "null observable arguments");
+    int r = check_ready(s, true);
+    if (r != HPMC_OK) return r;
+    Params P = make_params(s);
+    const double V = s->L * s->L * s->L;
+    auto run_cells = [&]() { return launch_build_cells(P, s->W, state_ref(s), false, s->stream); };
+    auto fetch = [&](int n, std::vector<unsigned long long>& h, int first) {
+        h.assign(static_cast<size_t>(n), 0ull);
+        hipError_t e = hipMemcpyAsync(h.data(), s->W.obs + first, static_cast<size_t>(n) * 8, hipMemcpyDeviceToHost,
+                                      s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        return e;
+    };
+    std::vector<unsigned long long> h;
+    if (kind == HPMC_OBS_GR) {
+        int nb = p->n_bins;
+        if (nb < 1 || nb > kObsWords || out_len < nb || !(p->r_max > 0.0) || p->r_max > s->halfL)
+            return fail(s, HPMC_EINVAL, "bad g(r) parameters");
+        hipError_t e = run_cells();
+        if (e == hipSuccess) e = launch_gr(P, s->W, nb, p->r_max, s->stream);
+        if (e == hipSuccess) e = fetch(nb, h, 0);
+        if (e != hipSuccess) return hip_fail(s, e, "g(r)");
+        double npair = 0.5 * static_cast<double>(s->N) * static_cast<double>(s->N - 1);
+        double dr = p->r_max / static_cast<double>(nb);
+        for (int b = 0; b < nb; ++b) {
+            double r0 = static_cast<double>(b) * dr, r1 = static_cast<double>(b + 1) * dr;
+            double shell = 4.0 / 3.0 * M_PI * (r1 * r1 * r1 - r0 * r0 * r0);
+            out[b] = static_cast<double>(h[static_cast<size_t>(b)]) / (npair * shell / V);
+        }
+        return HPMC_OK;
+    }
+    auto probes = [&](double scale, int slot) {
+        hipError_t e = launch_free_volume(P, s->W, p->n_probe, p->obs_seq, scale, slot, s->stream);
+        return e;
+    };
+    if (kind == HPMC_OBS_FREE_VOLUME) {
+        if (out_len < 3 || p->n_probe < 1 || p->n_probe > 0xFFFFFFFFll)
+            return fail(s, HPMC_EINVAL, "bad free-volume parameters");
+        hipError_t e = run_cells();
+        if (e == hipSuccess) e = launch_fill_u64(s->W.obs, 1, s->stream);
+        if (e == hipSuccess) e = probes(1.0, 0);
+        if (e == hipSuccess) e = fetch(1, h, 0);
+        if (e != hipSuccess) return hip_fail(s, e, "free volume");
+        double alpha = static_cast<double>(h[0]) / static_cast<double>(p->n_probe);
+        double phi_r = M_PI / 6.0 * s->d_dep * s->d_dep * s->d_dep * s->z_p;
+        out[0] = alpha;
+        out[1] = phi_r * alpha;
+        out[2] = static_cast<double>(h[0]);
+        return HPMC_OK;
+    }
+    if (kind == HPMC_OBS_SDF) {
+        int nb = p->n_bins;
+        if (nb < 2 || nb > kObsWords - 2 || out_len < 4 + nb || !(p->x_max > 0.0) || p->x_max >= 1.0 || p->n_fit < 2 ||
+            p->n_fit > nb || p->n_probe < 0 || p->n_probe > 0xFFFFFFFFll)
+            return fail(s, HPMC_EINVAL, "bad SDF parameters");
+        hipError_t e = run_cells();
+        if (e == hipSuccess) e = launch_sdf(P, s->W, nb, p->x_max, s->stream);
+        if (e == hipSuccess) e = fetch(nb, h, 0);
+        if (e != hipSuccess) return hip_fail(s, e, "SDF");
+        double* hist = out + 4;
+        double dx = p->x_max / static_cast<double>(nb);
+        for (int b = 0; b < nb; ++b)
+            hist[b] = static_cast<double>(h[static_cast<size_t>(b)]) / (static_cast<double>(s->N) * dx);
+        double sx = 0, sy = 0, sxx = 0, sxy = 0;
+        int nf = p->n_fit;
+        for (int b = 0; b < nf; ++b) {
+            double xb = (static_cast<double>(b) + 0.5) * dx;
+            sx += xb;
+            sy += hist[b];
+            sxx += xb * xb;
+            sxy += xb * hist[b];
+        }
+        double den = static_cast<double>(nf) * sxx - sx * sx;
+        double slope = (static_cast<double>(nf) * sxy - sx * sy) / den;
+        double s0 = (sy - slope * sx) / static_cast<double>(nf);
+        double rho = static_cast<double>(s->N) / V;
+        double bp_hard = rho * (1.0 + s0 / 6.0);
+        double bp_dep = 0.0;
+        if (s->z_p > 0.0 && p->n_probe > 0) {
+            const int s0slot = kObsWords - 2, s1slot = kObsWords - 1;
+            double sc = 1.0 + p->eps;
+            e = launch_fill_u64(s->W.obs + s0slot, 2, s->stream);
+            if (e == hipSuccess) e = probes(1.0, s0slot);
+            if (e == hipSuccess) e = probes(sc, s1slot);
+            if (e == hipSuccess) e = fetch(2, h, s0slot);
+            if (e != hipSuccess) return hip_fail(s, e, "SDF probes");
+            double g3 = sc * sc * sc;
+            double a0 = static_cast<double>(h[0]) / static_cast<double>(p->n_probe);
+            double a1 = static_cast<double>(h[1]) / static_cast<double>(p->n_probe);
+            bp_dep = s->z_p * ((g3 * a1 - a0) / (g3 - 1.0));
+        }
+        out[0] = bp_hard + bp_dep;
+        out[1] = bp_hard;
+        out[2] = bp_dep;
+        out[3] = s0;
+        return HPMC_OK;
+    }
+    return fail(s, HPMC_EINVAL, "unknown observable");
+}
+
+}  // extern "C"
+
+static_assert(sizeof(hpmc_move_record) == 40, "record layout");
+static_assert(sizeof(hpmc_counters) == kNumCounters * 8 + 16, "counter layout");

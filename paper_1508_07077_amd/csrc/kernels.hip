@@ -1,0 +1,1097 @@
+// kernels.hip -- HIP kernels of one implicit-depletant hard-particle Monte
+// Carlo sweep on CDNA4 (gfx950).
+//
+// Method: Glaser, Karas & Glotzer, arXiv:1508.07077.
+//   grid_kernel ............ random colour order and grid shift (Sec. III.E)
+//   bin / scan / scatter /
+//   sort / gather .......... cell list under the shifted checkerboard (Sec. III.E)
+//   phase_kernel ........... trial moves of one colour: proposal, hard overlap
+//                            (Eq. pacc), Poisson depletants in the circumsphere
+//                            (Sec. III.B step 2, Sec. III.C), classification and
+//                            early exit (Sec. III.B step 3, Fig. 2, App. A),
+//                            configurational bias (Sec. III.D, Eq. pacc_cb)
+//   scatter_back ........... cell-ordered records back to the caller's SoA state
+//
+// Mapping: one wavefront per active cell.  Lanes draw one Philox block each
+// (two ball candidates); accepted candidates get their depletant index from a
+// ballot + popcount prefix, so the wave resolves ~67 depletants per pass in
+// exactly the serial order.  Depletants that survive the cheap old-pose test
+// (a few per move) are tested against the cell stencil lane-per-neighbour,
+// and CB re-insertions of a blocking depletant run lane-per-trial.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+#include "rng.hpp"
+
+namespace hpmc {
+
+namespace {
+
+constexpr double kFar = 1.0e30;
+
+__device__ inline double mi(const Params& P, double d)
+{
+    if (d > P.halfL)
+        d -= P.L;
+    else if (d < -P.halfL)
+        d += P.L;
+    return d;
+}
+
+__device__ inline int cell_coord(const Params& P, double x, double g)
+{
+    double y = x - g;
+    if (y < 0.0) y += P.L;
+    int c = static_cast<int>(floor(y * P.inv_w));
+    if (c > P.n - 1) c = P.n - 1;
+    if (c < 0) c = 0;
+    return c;
+}
+
+__device__ inline int cell_of(const Params& P, double x, double y, double z, double g0, double g1, double g2)
+{
+    int cx = cell_coord(P, x, g0), cy = cell_coord(P, y, g1), cz = cell_coord(P, z, g2);
+    return cx + P.n * (cy + P.n * cz);
+}
+
+__device__ inline int lane_id() { return __lane_id(); }
+
+// number of set bits of `mask` in lanes below this one
+__device__ inline int bits_below(unsigned long long mask)
+{
+    return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
+}
+
+__device__ inline int ffs64(unsigned long long m) { return __builtin_ctzll(m); }
+
+__device__ inline uint32_t rdlane_u(uint32_t v, int l) { return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), l)); }
+
+__device__ inline double rdlane_d(double v, int l)
+{
+    unsigned long long b = __double_as_longlong(v);
+    uint32_t lo = rdlane_u(static_cast<uint32_t>(b), l);
+    uint32_t hi = rdlane_u(static_cast<uint32_t>(b >> 32), l);
+    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline int wave_excl_scan(int v, int& total)
+{
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int y = __shfl_up(x, d, 64);
+        if (lane_id() >= d) x += y;
+    }
+    total = __shfl(x, 63, 64);
+    return x - v;
+}
+
+__device__ inline int wave_sum(int v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+__device__ inline Words draw(const Params& P, uint32_t cell, uint32_t t, uint32_t purpose, uint32_t index)
+{
+    return philox(P.sweep, cell, (t << 8) | purpose, index, P.key0, P.key1);
+}
+
+// smallest k with F[k] >= u (F nondecreasing, F[kPoissonK-1] is a sentinel)
+__device__ inline int poisson_search(const double* F, double u)
+{
+    int lo = 0, hi = kPoissonK - 1;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (F[mid] >= u)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
+// 4-ball candidate: 25-bit fields, odd m in (-2^25, 2^25), accepted iff sum m^2 < 2^50
+__device__ inline bool ball4(Words w, double m[4])
+{
+    uint32_t ws[4] = {w.w0, w.w1, w.w2, w.w3};
+#pragma unroll
+    for (int a = 0; a < 4; ++a) m[a] = static_cast<double>(static_cast<int32_t>(2u * (ws[a] >> 7) + 1u) - (1 << 25));
+    double s = ((m[0] * m[0] + m[1] * m[1]) + m[2] * m[2]) + m[3] * m[3];
+    return s < 0x1p50;
+}
+
+// per-wave working set of the phase kernel
+struct WaveCtx {
+    int* list;          // stencil slots
+    double4* own_pos;   // own-cell records (updated on accept)
+    double4* own_q;
+    double* geo;        // per-trial geometry cache: D (3) [+ R (9)] per entry
+    int start, nc, nst;
+    int jslot;
+    Vec3 xn;
+};
+
+template <int KIND>
+struct Traits {
+    static constexpr bool oriented = (KIND != kSphere);
+    static constexpr int geo_stride = oriented ? 12 : 3;
+};
+
+// geometry of stencil entry i relative to the proposed position
+template <int KIND>
+__device__ inline void load_entry(const Params& P, const Work& W, const WaveCtx& c, int i, Vec3& D, Mat3& R)
+{
+    int slot = c.list[i];
+    double4 p, q;
+    bool own = slot >= c.start && slot < c.start + c.nc;
+    if (own)
+        p = c.own_pos[slot - c.start];
+    else
+        p = W.rpos[slot];
+    if (slot == c.jslot) {
+        D = v3(kFar, kFar, kFar);
+    } else {
+        D = v3(mi(P, p.x - c.xn.x), mi(P, p.y - c.xn.y), mi(P, p.z - c.xn.z));
+    }
+    if constexpr (Traits<KIND>::oriented) {
+        q = own ? c.own_q[slot - c.start] : W.rquat[slot];
+        R = quat_to_mat(q.x, q.y, q.z, q.w);
+    }
+}
+
+template <int KIND>
+__device__ inline void get_entry(const Params& P, const Work& W, const WaveCtx& c, int i, Vec3& D, Mat3& R)
+{
+    if (i < P.geo_cap) {
+        const double* g = c.geo + static_cast<size_t>(i) * Traits<KIND>::geo_stride;
+        D = v3(g[0], g[1], g[2]);
+        if constexpr (Traits<KIND>::oriented) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) R.m[k] = g[3 + k];
+        }
+    } else {
+        load_entry<KIND>(P, W, c, i, D, R);
+    }
+}
+
+// wave-cooperative: does a depletant at offset e overlap any stencil colloid?
+template <int KIND>
+__device__ inline bool stencil_hit_coop(const Params& P, const Work& W, const WaveCtx& c, Vec3 e)
+{
+    bool hit = false;
+    for (int i = lane_id(); i < c.nst; i += 64) {
+        Vec3 D;
+        Mat3 R;
+        get_entry<KIND>(P, W, c, i, D, R);
+        hit = hit || dep_ov<KIND>(P.S, e - D, R);
+    }
+    return __ballot(hit) != 0ull;
+}
+
+// per-lane: does the point p overlap any stencil colloid?  (all lanes read the
+// same entry at the same time: LDS broadcast)
+template <int KIND>
+__device__ inline bool stencil_hit_lane(const Params& P, const Work& W, const WaveCtx& c, Vec3 p, bool active)
+{
+    bool hit = !active;
+    for (int i = 0; i < c.nst; ++i) {
+        if (__ballot(!hit) == 0ull) break;
+        Vec3 D;
+        Mat3 R;
+        get_entry<KIND>(P, W, c, i, D, R);
+        if (!hit) hit = dep_ov<KIND>(P.S, p - D, R);
+    }
+    return hit && active;
+}
+
+// first accepted ball candidate of a CB sub-stream (at most 256 blocks),
+// lanes loop together until every active lane has its point
+__device__ inline Vec3 cb_point(const Params& P, uint32_t cell, uint32_t t, uint32_t purpose, uint32_t index_base,
+                                bool active)
+{
+    bool found = !active;
+    Vec3 f = v3(0.0, 0.0, 0.0);
+    for (uint32_t b = 0; b < 256u; ++b) {
+        if (!found) {
+            Words w = draw(P, cell, t, purpose, index_base + b);
+            double m0, m1, m2;
+            if (ball3(w.w0, w.w1, m0, m1, m2)) {
+                f = v3(P.s_ball * m0, P.s_ball * m1, P.s_ball * m2);
+                found = true;
+            } else if (ball3(w.w2, w.w3, m0, m1, m2)) {
+                f = v3(P.s_ball * m0, P.s_ball * m1, P.s_ball * m2);
+                found = true;
+            }
+        }
+        if (__ballot(!found) == 0ull) break;
+    }
+    return f;
+}
+
+struct TrialOut {
+    uint32_t n_dep, resolved, nblk, wf, wr, cbt;
+    int reason;
+    bool near;
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// grid, cells
+// ---------------------------------------------------------------------------
+__global__ void grid_kernel(Params P, Work W, int with_grid)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (!with_grid) {
+        for (int a = 0; a < 3; ++a) W.grid[a] = 0.0;
+        for (int i = 0; i < 8; ++i) W.perm[i] = i;
+        return;
+    }
+    Words a = draw(P, kNoCell, 0, kGrid, 0);
+    W.grid[0] = P.w * u01(a.w0);
+    W.grid[1] = P.w * u01(a.w1);
+    W.grid[2] = P.w * u01(a.w2);
+    Words b = draw(P, kNoCell, 0, kGrid, 1);
+    Words c = draw(P, kNoCell, 0, kGrid, 2);
+    uint32_t fy[7] = {b.w0, b.w1, b.w2, b.w3, c.w0, c.w1, c.w2};
+    int perm[8] = {0, 1, 2, 3, 4, 5, 6, 7};
+    for (int i = 7, f = 0; i >= 1; --i, ++f) {
+        int j = static_cast<int>(pick(fy[f], static_cast<uint32_t>(i + 1)));
+        int tmp = perm[i];
+        perm[i] = perm[j];
+        perm[j] = tmp;
+    }
+    for (int i = 0; i < 8; ++i) W.perm[i] = perm[i];
+}
+
+__global__ void fill_int_kernel(int* p, int n, int value)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = value;
+}
+
+__global__ void fill_u64_kernel(unsigned long long* p, int n)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+__global__ void bin_kernel(Params P, Work W, const double* __restrict__ pos)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.N) return;
+    int c = cell_of(P, pos[i], pos[P.N + i], pos[2 * P.N + i], W.grid[0], W.grid[1], W.grid[2]);
+    W.pcell[i] = c;
+    W.prank[i] = atomicAdd(&W.cell_count[c], 1);
+}
+
+// exclusive scan, 1024 elements per block of 256 threads
+__global__ __launch_bounds__(256) void scan_local_kernel(const int* __restrict__ in, int* __restrict__ out,
+                                                         int* __restrict__ totals, int n)
+{
+    __shared__ int wsum[4];
+    int base = blockIdx.x * 1024 + threadIdx.x * 4;
+    int v[4];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[k] = (base + k < n) ? in[base + k] : 0;
+        s += v[k];
+    }
+    int tot;
+    int ex = wave_excl_scan(s, tot);
+    int wv = threadIdx.x >> 6;
+    if (lane_id() == 0) wsum[wv] = tot;
+    __syncthreads();
+    int woff = 0;
+    for (int k = 0; k < wv; ++k) woff += wsum[k];
+    int run = woff + ex;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == 255) totals[blockIdx.x] = woff + ex + s;
+}
+
+__global__ __launch_bounds__(256) void scan_top_kernel(int* totals, int nblocks)
+{
+    __shared__ int wsum[4];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nblocks; base += 256) {
+        int i = base + threadIdx.x;
+        int v = (i < nblocks) ? totals[i] : 0;
+        int tot;
+        int ex = wave_excl_scan(v, tot);
+        int wv = threadIdx.x >> 6;
+        if (lane_id() == 0) wsum[wv] = tot;
+        __syncthreads();
+        int woff = 0, all = 0;
+        for (int k = 0; k < 4; ++k) {
+            if (k < wv) woff += wsum[k];
+            all += wsum[k];
+        }
+        if (i < nblocks) totals[i] = carry + woff + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += all;
+        __syncthreads();
+    }
+}
+
+__global__ void scan_add_kernel(int* out, const int* totals, int n, int total_all)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] += totals[i / 1024];
+    if (i == 0) out[n] = total_all;
+}
+
+__global__ void scatter_kernel(Params P, Work W)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.N) return;
+    W.order[W.cell_start[W.pcell[i]] + W.prank[i]] = i;
+}
+
+// members of each cell in ascending particle index (insertion sort; cells are small)
+__global__ void sort_kernel(Params P, Work W)
+{
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= P.ncells) return;
+    int s = W.cell_start[c], e = W.cell_start[c + 1];
+    for (int i = s + 1; i < e; ++i) {
+        int v = W.order[i];
+        int j = i - 1;
+        while (j >= s && W.order[j] > v) {
+            W.order[j + 1] = W.order[j];
+            --j;
+        }
+        W.order[j + 1] = v;
+    }
+}
+
+__global__ void gather_kernel(Params P, Work W, const double* __restrict__ pos, const double* __restrict__ quat)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= P.N) return;
+    int i = W.order[s];
+    W.rpos[s] = make_double4(pos[i], pos[P.N + i], pos[2 * P.N + i], static_cast<double>(i));
+    if (P.S.oriented)
+        W.rquat[s] = make_double4(quat[i], quat[P.N + i], quat[2 * P.N + i], quat[3 * P.N + i]);
+}
+
+__global__ void scatter_back_kernel(Params P, Work W, double* __restrict__ pos, double* __restrict__ quat)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= P.N) return;
+    double4 r = W.rpos[s];
+    int i = static_cast<int>(r.w);
+    pos[i] = r.x;
+    pos[P.N + i] = r.y;
+    pos[2 * P.N + i] = r.z;
+    if (P.S.oriented) {
+        double4 q = W.rquat[s];
+        quat[i] = q.x;
+        quat[P.N + i] = q.y;
+        quat[2 * P.N + i] = q.z;
+        quat[3 * P.N + i] = q.w;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// one colour of the checkerboard: every active cell runs its trials
+// ---------------------------------------------------------------------------
+template <int KIND>
+__global__ __launch_bounds__(256) void phase_kernel(Params P, Work W, int phase)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    double* sF = reinterpret_cast<double*>(smem);
+    for (int i = threadIdx.x; i < kPoissonK; i += blockDim.x) sF[i] = W.F[i];
+    __syncthreads();
+
+    const int lane = lane_id();
+    const int wv = threadIdx.x >> 6;
+    unsigned char* wbase = smem + kPoissonK * sizeof(double) + static_cast<size_t>(wv) * P.wave_lds;
+    WaveCtx c;
+    c.list = reinterpret_cast<int*>(wbase);
+    c.own_pos = reinterpret_cast<double4*>(wbase + P.off_own_pos);
+    c.own_q = reinterpret_cast<double4*>(wbase + P.off_own_q);
+    c.geo = reinterpret_cast<double*>(wbase + P.off_geo);
+    constexpr int GS = Traits<KIND>::geo_stride;
+    constexpr bool ORI = Traits<KIND>::oriented;
+
+    unsigned long long cnt[kNumCounters];
+#pragma unroll
+    for (int k = 0; k < kNumCounters; ++k) cnt[k] = 0ull;
+
+    const int colour = W.perm[phase];
+    const int gw = blockIdx.x * P.waves_per_block + wv;
+    const int nwaves = gridDim.x * P.waves_per_block;
+    const double g0 = W.grid[0], g1 = W.grid[1], g2 = W.grid[2];
+    const int noff = (P.n == 2) ? 2 : 3;
+    const int ncl = noff * noff * noff;
+
+    for (int a = gw; a < P.active_cells; a += nwaves) {
+        const int ax = a % P.h, ay = (a / P.h) % P.h, az = a / (P.h * P.h);
+        const int cx = 2 * ax + (colour & 1), cy = 2 * ay + ((colour >> 1) & 1), cz = 2 * az + ((colour >> 2) & 1);
+        const int C = cx + P.n * (cy + P.n * cz);
+        c.start = W.cell_start[C];
+        c.nc = W.cell_start[C + 1] - c.start;
+        if (c.nc == 0) continue;
+        if (c.nc > P.own_cap) {
+            if (lane == 0) atomicOr(W.flags, kFlagOwnOverflow);
+            continue;
+        }
+        // own-cell records into LDS (they change as moves are accepted)
+        for (int i = lane; i < c.nc; i += 64) {
+            c.own_pos[i] = W.rpos[c.start + i];
+            if constexpr (ORI) c.own_q[i] = W.rquat[c.start + i];
+        }
+        // stencil: the de-duplicated 27 (n > 2) or 8 (n = 2) cells around C
+        int es = 0, ec = 0;
+        if (lane < ncl) {
+            int dx = lane % noff, dy = (lane / noff) % noff, dz = lane / (noff * noff);
+            if (noff == 3) {
+                dx -= 1;
+                dy -= 1;
+                dz -= 1;
+            }
+            int ex = (cx + dx + P.n) % P.n, ey = (cy + dy + P.n) % P.n, ez = (cz + dz + P.n) % P.n;
+            int e = ex + P.n * (ey + P.n * ez);
+            es = W.cell_start[e];
+            ec = W.cell_start[e + 1] - es;
+        }
+        int nst;
+        int off = wave_excl_scan(ec, nst);
+        if (nst > P.list_cap) {
+            if (lane == 0) atomicOr(W.flags, kFlagListOverflow);
+            continue;
+        }
+        for (int k = 0; k < ec; ++k) c.list[off + k] = es + k;
+        c.nst = nst;
+        wave_sync();
+
+        const int ntr = P.n_select * c.nc;
+        for (int t = 0; t < ntr; ++t) {
+            // --- per-trial draws packed across lanes ---------------------------
+            uint32_t purpose = 0, index = 0;
+            if (lane == 0) {
+                purpose = kSelect;
+            } else if (lane == 1) {
+                purpose = kTrans;
+            } else if (lane == 2) {
+                purpose = kAccept;
+            } else if (lane < 32) {
+                purpose = kPoisson;
+                index = static_cast<uint32_t>(lane - 3);
+            } else {
+                purpose = kRot;
+                index = static_cast<uint32_t>(lane - 32);
+            }
+            Words w = draw(P, static_cast<uint32_t>(C), static_cast<uint32_t>(t), purpose, index);
+            const uint32_t sel0 = rdlane_u(w.w0, 0), sel1 = rdlane_u(w.w1, 0);
+            const int jl = static_cast<int>(pick(sel0, static_cast<uint32_t>(c.nc)));
+            const bool rotate = ORI && P.p_rot > 0.0 && u01(sel1) < P.p_rot;
+            c.jslot = c.start + jl;
+            const double4 pj = c.own_pos[jl];
+            double4 qj = make_double4(1.0, 0.0, 0.0, 0.0);
+            if constexpr (ORI) qj = c.own_q[jl];
+            Vec3 xn = v3(pj.x, pj.y, pj.z);
+            double qn[4] = {qj.x, qj.y, qj.z, qj.w};
+            if (!rotate) {
+                double xs[3] = {pj.x, pj.y, pj.z};
+                uint32_t tw[3] = {rdlane_u(w.w0, 1), rdlane_u(w.w1, 1), rdlane_u(w.w2, 1)};
+                double xo[3];
+#pragma unroll
+                for (int ax3 = 0; ax3 < 3; ++ax3) {
+                    double v = xs[ax3] + P.d_trans * sym01(tw[ax3]);
+                    if (v >= P.L)
+                        v -= P.L;
+                    else if (v < 0.0)
+                        v += P.L;
+                    xo[ax3] = v;
+                }
+                xn = v3(xo[0], xo[1], xo[2]);
+            } else {
+                // first accepted 4-ball candidate over the ROT blocks
+                double m[4];
+                bool acc = (lane >= 32) && ball4(w, m);
+                unsigned long long am = __ballot(acc);
+                int src = -1;
+                uint32_t vw[4] = {0, 0, 0, 0};
+                if (am) {
+                    src = ffs64(am);
+                    vw[0] = rdlane_u(w.w0, src);
+                    vw[1] = rdlane_u(w.w1, src);
+                    vw[2] = rdlane_u(w.w2, src);
+                    vw[3] = rdlane_u(w.w3, src);
+                } else {
+                    for (uint32_t base = 32; base < 256u && src < 0; base += 64) {
+                        Words r = draw(P, static_cast<uint32_t>(C), static_cast<uint32_t>(t), kRot, base + lane);
+                        bool ok = (base + lane < 256u) && ball4(r, m);
+                        unsigned long long om = __ballot(ok);
+                        if (om) {
+                            src = ffs64(om);
+                            vw[0] = rdlane_u(r.w0, src);
+                            vw[1] = rdlane_u(r.w1, src);
+                            vw[2] = rdlane_u(r.w2, src);
+                            vw[3] = rdlane_u(r.w3, src);
+                        }
+                    }
+                }
+                if (src >= 0) {
+                    Words vv{vw[0], vw[1], vw[2], vw[3]};
+                    ball4(vv, m);
+                    double qq[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) qq[k] = qn[k] + P.a_rot * (m[k] * 0x1p-25);
+                    double nrm = sqrt(((qq[0] * qq[0] + qq[1] * qq[1]) + qq[2] * qq[2]) + qq[3] * qq[3]);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) qn[k] = qq[k] / nrm;
+                }
+            }
+            c.xn = xn;
+
+            TrialOut o{0, 0, 0, 0, 0, 0, 0, false};
+            // --- cell exit (particles may not leave their cell, Sec. III.E) ----
+            if (cell_of(P, xn.x, xn.y, xn.z, g0, g1, g2) != C) {
+                o.reason = 1;
+            } else {
+                // --- geometry cache of the stencil relative to x' ----------------
+                const int ng = c.nst < P.geo_cap ? c.nst : P.geo_cap;
+                for (int i = lane; i < ng; i += 64) {
+                    Vec3 D;
+                    Mat3 R;
+                    load_entry<KIND>(P, W, c, i, D, R);
+                    double* g = c.geo + static_cast<size_t>(i) * GS;
+                    g[0] = D.x;
+                    g[1] = D.y;
+                    g[2] = D.z;
+                    if constexpr (ORI) {
+#pragma unroll
+                        for (int k = 0; k < 9; ++k) g[3 + k] = R.m[k];
+                    }
+                }
+                wave_sync();
+                Mat3 Rn, Ro;
+                if constexpr (ORI) {
+                    Rn = quat_to_mat(qn[0], qn[1], qn[2], qn[3]);
+                    Ro = quat_to_mat(qj.x, qj.y, qj.z, qj.w);
+                }
+                // --- hard colloid overlap: min(1, exp(-beta dH_cc)) ---------------
+                bool hit = false, nearc = false;
+                int checks = 0;
+                for (int i = lane; i < c.nst; i += 64) {
+                    Vec3 D;
+                    Mat3 R;
+                    get_entry<KIND>(P, W, c, i, D, R);
+                    PairResult pr = pair_ov<KIND>(P.S, D, Rn, R);
+                    hit = hit || pr.overlap;
+                    nearc = nearc || pr.near;
+                    checks++;
+                }
+                o.near = __ballot(nearc) != 0ull;
+                cnt[cOverlapChecks] += static_cast<unsigned long long>(wave_sum(checks));
+                if (__ballot(hit) != 0ull) {
+                    o.reason = 2;
+                } else if (P.has_dep) {
+                    // --- Poisson number of depletants in V_0 = B(x', R0) ----------
+                    int kc = 0;
+                    if (lane >= 3 && lane < 32 && lane - 3 < P.n_chunks) kc = poisson_search(sF, u52(w.w0, w.w1));
+                    for (int base = 29; base < P.n_chunks; base += 64) {
+                        int ci = base + lane;
+                        if (ci < P.n_chunks) {
+                            Words pw = draw(P, static_cast<uint32_t>(C), static_cast<uint32_t>(t), kPoisson,
+                                            static_cast<uint32_t>(ci));
+                            kc += poisson_search(sF, u52(pw.w0, pw.w1));
+                        }
+                    }
+                    const uint32_t Np = static_cast<uint32_t>(wave_sum(kc));
+                    o.n_dep = Np;
+                    const double au = u52(rdlane_u(w.w0, 2), rdlane_u(w.w1, 2));
+                    const Vec3 Dold = v3(mi(P, pj.x - xn.x), mi(P, pj.y - xn.y), mi(P, pj.z - xn.z));
+                    const Vec3 zero3 = v3(0.0, 0.0, 0.0);
+                    double ratio = 1.0;
+                    bool done = false;
+                    uint32_t kbase = 0, blk = 0;
+                    while (!done && kbase < Np && blk < (1u << 30)) {
+                        Words dw = draw(P, static_cast<uint32_t>(C), static_cast<uint32_t>(t), kDepl, blk + lane);
+                        double a0, a1, a2, b0, b1, b2;
+                        bool acc0 = ball3(dw.w0, dw.w1, a0, a1, a2);
+                        bool acc1 = ball3(dw.w2, dw.w3, b0, b1, b2);
+                        unsigned long long m0 = __ballot(acc0), m1 = __ballot(acc1);
+                        uint32_t k0 = kbase + static_cast<uint32_t>(bits_below(m0) + bits_below(m1));
+                        uint32_t k1 = k0 + (acc0 ? 1u : 0u);
+                        bool v0 = acc0 && k0 < Np, v1 = acc1 && k1 < Np;
+                        Vec3 e0 = v3(P.s_ball * a0, P.s_ball * a1, P.s_ball * a2);
+                        Vec3 e1 = v3(P.s_ball * b0, P.s_ball * b1, P.s_ball * b2);
+                        // irrelevant (misses M') or ignored by the old pose
+                        if (v0) {
+                            if constexpr (ORI) v0 = dep_ov<KIND>(P.S, e0, Rn);
+                            if (v0) v0 = !dep_ov<KIND>(P.S, e0 - Dold, Ro);
+                        }
+                        if (v1) {
+                            if constexpr (ORI) v1 = dep_ov<KIND>(P.S, e1, Rn);
+                            if (v1) v1 = !dep_ov<KIND>(P.S, e1 - Dold, Ro);
+                        }
+                        unsigned long long r0 = __ballot(v0), r1 = __ballot(v1);
+                        // survivors in ascending depletant index: lane order, candidate 0 before 1
+                        while ((r0 | r1) && !done) {
+                            int l0 = r0 ? ffs64(r0) : 64, l1 = r1 ? ffs64(r1) : 64;
+                            int src, cand;
+                            if (l0 <= l1) {
+                                src = l0;
+                                cand = 0;
+                                r0 &= ~(1ull << l0);
+                            } else {
+                                src = l1;
+                                cand = 1;
+                                r1 &= ~(1ull << l1);
+                            }
+                            src = __builtin_amdgcn_readfirstlane(src);
+                            Vec3 es = cand ? e1 : e0;
+                            es = v3(rdlane_d(es.x, src), rdlane_d(es.y, src), rdlane_d(es.z, src));
+                            uint32_t ks = rdlane_u(cand ? k1 : k0, src);
+                            if (stencil_hit_coop<KIND>(P, W, c, es)) continue;  // ignored
+                            // blocking: free in M, overlapping M'
+                            o.nblk++;
+                            if (P.n_trial == 0) {
+                                o.reason = 3;
+                                o.resolved = ks + 1;
+                                done = true;
+                                break;
+                            }
+                            // configurational bias: n_trial forward + (n_trial - 1) reverse insertions
+                            const int ntot = 2 * P.n_trial - 1;
+                            uint32_t Wf = 0, Wr = 0;
+                            for (int base = 0; base < ntot; base += 64) {
+                                int idx = base + lane;
+                                bool active = idx < ntot;
+                                bool fwd = idx < P.n_trial;
+                                int ti = fwd ? idx : idx - P.n_trial;
+                                uint32_t ib = (ks << 16) | (static_cast<uint32_t>(ti) << 8);
+                                Vec3 f = cb_point(P, static_cast<uint32_t>(C), static_cast<uint32_t>(t),
+                                                  fwd ? kCbFwd : kCbRev, ib, active);
+                                bool valid = active;
+                                Vec3 pt = fwd ? (Dold + f) : f;
+                                if (valid) {
+                                    if (fwd) {
+                                        if constexpr (ORI) valid = dep_ov<KIND>(P.S, f, Ro);
+                                        if (valid) valid = !dep_ov<KIND>(P.S, pt, Rn);
+                                    } else {
+                                        if constexpr (ORI) valid = dep_ov<KIND>(P.S, f, Rn);
+                                        if (valid) valid = !dep_ov<KIND>(P.S, f - Dold, Ro);
+                                    }
+                                }
+                                valid = valid && !stencil_hit_lane<KIND>(P, W, c, pt, valid);
+                                Wf += static_cast<uint32_t>(__popcll(__ballot(valid && fwd)));
+                                Wr += static_cast<uint32_t>(__popcll(__ballot(valid && !fwd)));
+                            }
+                            o.wf += Wf;
+                            if (Wf == 0) {
+                                o.reason = 4;
+                                o.resolved = ks + 1 + o.cbt + static_cast<uint32_t>(P.n_trial);
+                                o.cbt += static_cast<uint32_t>(P.n_trial);
+                                done = true;
+                                break;
+                            }
+                            o.wr += Wr;
+                            ratio = ratio * (static_cast<double>(Wf) / static_cast<double>(1 + Wr));
+                            o.cbt += static_cast<uint32_t>(ntot);
+                        }
+                        kbase += static_cast<uint32_t>(__popcll(m0) + __popcll(m1));
+                        blk += 64;
+                    }
+                    (void)zero3;
+                    if (!done) {
+                        o.resolved = Np + o.cbt;
+                        if (o.nblk > 0 && !(au < ratio)) o.reason = 5;
+                    }
+                }
+            }
+            // --- accept / commit / record ---------------------------------------
+            if (o.reason == 0 && lane == 0) {
+                c.own_pos[jl] = make_double4(xn.x, xn.y, xn.z, pj.w);
+                if constexpr (ORI) c.own_q[jl] = make_double4(qn[0], qn[1], qn[2], qn[3]);
+            }
+            wave_sync();
+            cnt[cTrials] += 1;
+            switch (o.reason) {
+            case 0: cnt[cAccepts] += 1; break;
+            case 1: cnt[cRejCellExit] += 1; break;
+            case 2: cnt[cRejOverlap] += 1; break;
+            case 3: cnt[cRejDepletant] += 1; break;
+            case 4: cnt[cRejCbZero] += 1; break;
+            default: cnt[cRejCbMetro] += 1; break;
+            }
+            cnt[cDrawn] += o.n_dep;
+            cnt[cResolved] += o.resolved;
+            cnt[cCbTrials] += o.cbt;
+            cnt[cNearContact] += o.near ? 1 : 0;
+            if (P.trace && lane == 0) {
+                uint32_t* r = reinterpret_cast<uint32_t*>(static_cast<unsigned char*>(W.trace) +
+                                                          (static_cast<size_t>(P.n_select) * c.start + t) * 40);
+                r[0] = P.sweep;
+                r[1] = static_cast<uint32_t>(C);
+                r[2] = static_cast<uint32_t>(t);
+                r[3] = static_cast<uint32_t>(pj.w);
+                r[4] = o.n_dep;
+                r[5] = o.resolved;
+                r[6] = o.nblk;
+                r[7] = o.wf;
+                r[8] = o.wr;
+                r[9] = static_cast<uint32_t>(phase) | (static_cast<uint32_t>(o.reason) << 8) |
+                       (static_cast<uint32_t>(rotate ? 1 : 0) << 16) | (static_cast<uint32_t>(o.near ? 1 : 0) << 24);
+            }
+        }
+        // own-cell records back to HBM
+        for (int i = lane; i < c.nc; i += 64) {
+            W.rpos[c.start + i] = c.own_pos[i];
+            if constexpr (ORI) W.rquat[c.start + i] = c.own_q[i];
+        }
+        wave_sync();
+    }
+    if (lane == 0) {
+        unsigned long long* dst = W.counters + static_cast<size_t>(gw % kCounterCopies) * kCounterStride;
+#pragma unroll
+        for (int k = 0; k < kNumCounters; ++k)
+            if (cnt[k]) atomicAdd(dst + k, cnt[k]);
+    }
+}
+
+__global__ void reduce_counters_kernel(Work W)
+{
+    int k = threadIdx.x;
+    if (k >= kNumCounters) return;
+    unsigned long long s = 0;
+    for (int c = 1; c < kCounterCopies; ++c) s += W.counters[static_cast<size_t>(c) * kCounterStride + k];
+    W.counters[k] += s;
+}
+
+// hard-core check of a state: pairs (slot order) that overlap
+__global__ void overlap_count_kernel(Params P, Work W)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= P.N) return;
+    double4 a = W.rpos[s];
+    int ia = static_cast<int>(a.w);
+    Mat3 RA, RB;
+    if (P.S.oriented) {
+        double4 q = W.rquat[s];
+        RA = quat_to_mat(q.x, q.y, q.z, q.w);
+    }
+    int cx = cell_coord(P, a.x, 0.0), cy = cell_coord(P, a.y, 0.0), cz = cell_coord(P, a.z, 0.0);
+    const int noff = (P.n == 2) ? 2 : 3;
+    unsigned long long cntv = 0;
+    for (int l = 0; l < noff * noff * noff; ++l) {
+        int dx = l % noff, dy = (l / noff) % noff, dz = l / (noff * noff);
+        if (noff == 3) {
+            dx -= 1;
+            dy -= 1;
+            dz -= 1;
+        }
+        int e = (cx + dx + P.n) % P.n + P.n * ((cy + dy + P.n) % P.n + P.n * ((cz + dz + P.n) % P.n));
+        for (int q = W.cell_start[e]; q < W.cell_start[e + 1]; ++q) {
+            double4 b = W.rpos[q];
+            int ib = static_cast<int>(b.w);
+            if (ib <= ia) continue;
+            Vec3 d = v3(mi(P, b.x - a.x), mi(P, b.y - a.y), mi(P, b.z - a.z));
+            if (P.S.oriented) {
+                double4 qb = W.rquat[q];
+                RB = quat_to_mat(qb.x, qb.y, qb.z, qb.w);
+            }
+            if (pair_overlap(P.S, d, RA, RB).overlap) cntv++;
+        }
+    }
+    if (cntv) atomicAdd(W.obs, cntv);
+}
+
+// ---------------------------------------------------------------------------
+// observables of the current state (cell list built with zero shift)
+// ---------------------------------------------------------------------------
+namespace {
+
+// cells within +-k of c along one axis, de-duplicated when 2k+1 >= n
+__device__ inline int axis_span(int n, int k, int& first)
+{
+    if (2 * k + 1 >= n) {
+        first = 0;
+        return n;
+    }
+    first = -k;
+    return 2 * k + 1;
+}
+
+__device__ inline int wrap_cell(int c, int n) { return ((c % n) + n) % n; }
+
+}  // namespace
+
+// pair-distance histogram (pairs i < j), W.obs[0..n_bins)
+__global__ __launch_bounds__(256) void gr_kernel(Params P, Work W, int n_bins, double r_max, int k)
+{
+    extern __shared__ unsigned long long hist[];
+    for (int b = threadIdx.x; b < n_bins; b += blockDim.x) hist[b] = 0ull;
+    __syncthreads();
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < P.N) {
+        double4 a = W.rpos[s];
+        int ia = static_cast<int>(a.w);
+        int cx = cell_coord(P, a.x, 0.0), cy = cell_coord(P, a.y, 0.0), cz = cell_coord(P, a.z, 0.0);
+        double inv_dr = static_cast<double>(n_bins) / r_max;
+        double rm2 = r_max * r_max;
+        int fx, fy, fz;
+        int nx = axis_span(P.n, k, fx), ny = axis_span(P.n, k, fy), nz = axis_span(P.n, k, fz);
+        for (int dz = 0; dz < nz; ++dz)
+            for (int dy = 0; dy < ny; ++dy)
+                for (int dx = 0; dx < nx; ++dx) {
+                    int ex = (nx == P.n) ? dx : wrap_cell(cx + fx + dx, P.n);
+                    int ey = (ny == P.n) ? dy : wrap_cell(cy + fy + dy, P.n);
+                    int ez = (nz == P.n) ? dz : wrap_cell(cz + fz + dz, P.n);
+                    int e = ex + P.n * (ey + P.n * ez);
+                    for (int q = W.cell_start[e]; q < W.cell_start[e + 1]; ++q) {
+                        double4 b = W.rpos[q];
+                        if (static_cast<int>(b.w) <= ia) continue;
+                        Vec3 d = v3(mi(P, b.x - a.x), mi(P, b.y - a.y), mi(P, b.z - a.z));
+                        double r2 = dot(d, d);
+                        if (r2 >= rm2) continue;
+                        double r = sqrt(r2);
+                        if (r < r_max) {
+                            int bin = static_cast<int>(floor(r * inv_dr));
+                            if (bin < n_bins) atomicAdd(&hist[bin], 1ull);
+                        }
+                    }
+                }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < n_bins; b += blockDim.x)
+        if (hist[b]) atomicAdd(&W.obs[b], hist[b]);
+}
+
+// uniform probes that overlap no colloid (displacements scaled by `scale`)
+__global__ __launch_bounds__(256) void free_volume_kernel(Params P, Work W, int64_t n_probe, uint32_t seq,
+                                                          double scale, int slot)
+{
+    int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    int free_ = 0;
+    if (p < n_probe) {
+        Words w = philox(seq, kNoCell, kObsFv, static_cast<uint32_t>(p), P.key0, P.key1);
+        double X = P.L * u01(w.w0), Y = P.L * u01(w.w1), Z = P.L * u01(w.w2);
+        int cx = cell_coord(P, X, 0.0), cy = cell_coord(P, Y, 0.0), cz = cell_coord(P, Z, 0.0);
+        const int noff = (P.n == 2) ? 2 : 3;
+        bool hit = false;
+        for (int l = 0; l < noff * noff * noff && !hit; ++l) {
+            int dx = l % noff, dy = (l / noff) % noff, dz = l / (noff * noff);
+            if (noff == 3) {
+                dx -= 1;
+                dy -= 1;
+                dz -= 1;
+            }
+            int e = wrap_cell(cx + dx, P.n) + P.n * (wrap_cell(cy + dy, P.n) + P.n * wrap_cell(cz + dz, P.n));
+            for (int q = W.cell_start[e]; q < W.cell_start[e + 1] && !hit; ++q) {
+                double4 b = W.rpos[q];
+                Vec3 v = v3(mi(P, X - b.x), mi(P, Y - b.y), mi(P, Z - b.z));
+                if (scale != 1.0) v = v3(v.x * scale, v.y * scale, v.z * scale);
+                Mat3 R;
+                if (P.S.oriented) {
+                    double4 qq = W.rquat[q];
+                    R = quat_to_mat(qq.x, qq.y, qq.z, qq.w);
+                }
+                hit = dep_overlap(P.S, v, R);
+            }
+        }
+        free_ = hit ? 0 : 1;
+    }
+    int tot = wave_sum(free_);
+    if (lane_id() == 0 && tot) atomicAdd(&W.obs[slot], static_cast<unsigned long long>(tot));
+}
+
+// per-particle smallest compression of a neighbour separation at which the
+// pair overlaps (scale-distribution function); histogram in W.obs
+__global__ __launch_bounds__(128) void sdf_kernel(Params P, Work W, int n_bins, double x_max, int k)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= P.N) return;
+    double4 a = W.rpos[s];
+    int ia = static_cast<int>(a.w);
+    Mat3 RA, RB;
+    if (P.S.oriented) {
+        double4 q = W.rquat[s];
+        RA = quat_to_mat(q.x, q.y, q.z, q.w);
+    }
+    int cx = cell_coord(P, a.x, 0.0), cy = cell_coord(P, a.y, 0.0), cz = cell_coord(P, a.z, 0.0);
+    double lim_s = 2.0 * P.S.rcirc / (1.0 - x_max);
+    double lim = 2.0 * P.S.rcirc;
+    double xmin = x_max;
+    int fx, fy, fz;
+    int nx = axis_span(P.n, k, fx), ny = axis_span(P.n, k, fy), nz = axis_span(P.n, k, fz);
+    for (int dz = 0; dz < nz; ++dz)
+        for (int dy = 0; dy < ny; ++dy)
+            for (int dx = 0; dx < nx; ++dx) {
+                int ex = (nx == P.n) ? dx : wrap_cell(cx + fx + dx, P.n);
+                int ey = (ny == P.n) ? dy : wrap_cell(cy + fy + dy, P.n);
+                int ez = (nz == P.n) ? dz : wrap_cell(cz + fz + dz, P.n);
+                int e = ex + P.n * (ey + P.n * ez);
+                for (int q = W.cell_start[e]; q < W.cell_start[e + 1]; ++q) {
+                    double4 b = W.rpos[q];
+                    if (static_cast<int>(b.w) == ia) continue;
+                    Vec3 d = v3(mi(P, b.x - a.x), mi(P, b.y - a.y), mi(P, b.z - a.z));
+                    double dd = dot(d, d);
+                    if (dd >= lim_s * lim_s) continue;
+                    double x;
+                    if (P.S.kind == kSphere) {
+                        double r = sqrt(dd);
+                        x = 1.0 - P.S.a * 2.0 / r;
+                        if (x > x_max) x = x_max;
+                    } else {
+                        if (P.S.oriented) {
+                            double4 qb = W.rquat[q];
+                            RB = quat_to_mat(qb.x, qb.y, qb.z, qb.w);
+                        }
+                        double f = 1.0 - x_max;
+                        Vec3 dm = v3(d.x * f, d.y * f, d.z * f);
+                        if (dot(dm, dm) >= lim * lim || !mpr_overlap(P.S, dm, RA, RB).overlap) {
+                            x = x_max;
+                        } else {
+                            double lo = 0.0, hi = x_max;
+                            for (int it = 0; it < 40; ++it) {
+                                double mid = 0.5 * (lo + hi);
+                                double fm = 1.0 - mid;
+                                Vec3 dx3 = v3(d.x * fm, d.y * fm, d.z * fm);
+                                bool ov = dot(dx3, dx3) < lim * lim && mpr_overlap(P.S, dx3, RA, RB).overlap;
+                                if (ov)
+                                    hi = mid;
+                                else
+                                    lo = mid;
+                            }
+                            x = hi;
+                        }
+                    }
+                    if (x < xmin) xmin = x;
+                }
+            }
+    if (xmin < x_max) {
+        int bin = static_cast<int>(floor(xmin * (static_cast<double>(n_bins) / x_max)));
+        if (bin < n_bins) atomicAdd(&W.obs[bin], 1ull);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline int blocks_for(int n, int bs) { return (n + bs - 1) / bs; }
+
+hipError_t launch_fill_int(int* p, int n, int value, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_int_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, stream, p, n, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, int n, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, stream, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_cells(const Params& P, const Work& W, const StateRef& st, bool with_grid, hipStream_t stream)
+{
+    hipLaunchKernelGGL(grid_kernel, dim3(1), dim3(64), 0, stream, P, W, with_grid ? 1 : 0);
+    hipError_t e = launch_fill_int(W.cell_count, P.ncells, 0, stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(bin_kernel, dim3(blocks_for(P.N, 256)), dim3(256), 0, stream, P, W,
+                       static_cast<const double*>(st.pos));
+    int nb = blocks_for(P.ncells, 1024);
+    hipLaunchKernelGGL(scan_local_kernel, dim3(nb), dim3(256), 0, stream, static_cast<const int*>(W.cell_count),
+                       W.cell_start, W.scan_tmp, P.ncells);
+    hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(256), 0, stream, W.scan_tmp, nb);
+    hipLaunchKernelGGL(scan_add_kernel, dim3(blocks_for(P.ncells, 256)), dim3(256), 0, stream, W.cell_start,
+                       static_cast<const int*>(W.scan_tmp), P.ncells, P.N);
+    hipLaunchKernelGGL(scatter_kernel, dim3(blocks_for(P.N, 256)), dim3(256), 0, stream, P, W);
+    hipLaunchKernelGGL(sort_kernel, dim3(blocks_for(P.ncells, 256)), dim3(256), 0, stream, P, W);
+    hipLaunchKernelGGL(gather_kernel, dim3(blocks_for(P.N, 256)), dim3(256), 0, stream, P, W,
+                       static_cast<const double*>(st.pos), static_cast<const double*>(st.quat));
+    return hipGetLastError();
+}
+
+hipError_t launch_phase(const Params& P, const Work& W, int phase, hipStream_t stream)
+{
+    size_t lds = kPoissonK * sizeof(double) + static_cast<size_t>(P.waves_per_block) * P.wave_lds;
+    int waves = P.active_cells;
+    int max_waves = 256 * 32;
+    if (waves > max_waves) waves = max_waves;
+    int blocks = blocks_for(waves, P.waves_per_block);
+    dim3 bs(64 * P.waves_per_block);
+    switch (P.S.kind) {
+    case kSphere: hipLaunchKernelGGL(phase_kernel<kSphere>, dim3(blocks), bs, lds, stream, P, W, phase); break;
+    case kHemisphere:
+        hipLaunchKernelGGL(phase_kernel<kHemisphere>, dim3(blocks), bs, lds, stream, P, W, phase);
+        break;
+    default: hipLaunchKernelGGL(phase_kernel<kDiscoid>, dim3(blocks), bs, lds, stream, P, W, phase); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_back(const Params& P, const Work& W, const StateRef& st, hipStream_t stream)
+{
+    hipLaunchKernelGGL(scatter_back_kernel, dim3(blocks_for(P.N, 256)), dim3(256), 0, stream, P, W, st.pos, st.quat);
+    return hipGetLastError();
+}
+
+hipError_t launch_overlap_count(const Params& P, const Work& W, hipStream_t stream)
+{
+    hipLaunchKernelGGL(overlap_count_kernel, dim3(blocks_for(P.N, 128)), dim3(128), 0, stream, P, W);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_counters(const Work& W, hipStream_t stream)
+{
+    hipLaunchKernelGGL(reduce_counters_kernel, dim3(1), dim3(64), 0, stream, W);
+    return hipGetLastError();
+}
+
+}  // namespace hpmc
+
+namespace hpmc {
+
+hipError_t launch_gr(const Params& P, const Work& W, int n_bins, double r_max, hipStream_t stream)
+{
+    hipError_t e = launch_fill_u64(W.obs, n_bins, stream);
+    if (e != hipSuccess) return e;
+    int k = static_cast<int>(ceil(r_max * P.inv_w));
+    hipLaunchKernelGGL(gr_kernel, dim3(blocks_for(P.N, 256)), dim3(256), n_bins * sizeof(unsigned long long), stream,
+                       P, W, n_bins, r_max, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_free_volume(const Params& P, const Work& W, int64_t n_probe, uint32_t seq, double scale, int slot,
+                              hipStream_t stream)
+{
+    int64_t blocks = (n_probe + 255) / 256;
+    hipLaunchKernelGGL(free_volume_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, P, W, n_probe,
+                       seq, scale, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_sdf(const Params& P, const Work& W, int n_bins, double x_max, hipStream_t stream)
+{
+    hipError_t e = launch_fill_u64(W.obs, n_bins, stream);
+    if (e != hipSuccess) return e;
+    double lim_s = 2.0 * P.S.rcirc / (1.0 - x_max);
+    int k = static_cast<int>(ceil(lim_s * P.inv_w));
+    hipLaunchKernelGGL(sdf_kernel, dim3(blocks_for(P.N, 128)), dim3(128), 0, stream, P, W, n_bins, x_max, k);
+    return hipGetLastError();
+}
+
+}  // namespace hpmc

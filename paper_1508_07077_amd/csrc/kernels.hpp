@@ -1,0 +1,98 @@
+// kernels.hpp -- launch interface between the C-ABI host code and the HIP
+// kernels of one implicit-depletant sweep.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "geom.hpp"
+
+namespace hpmc {
+
+constexpr int kPoissonK = 1024;      // inverse-CDF table length (last entry is a sentinel)
+constexpr int kCounterCopies = 256;  // spread copies of the counters (atomic contention)
+constexpr int kNumCounters = 13;
+constexpr int kCounterStride = 16;
+
+enum CounterIdx : int {
+    cTrials = 0,
+    cAccepts,
+    cRejCellExit,
+    cRejOverlap,
+    cRejDepletant,
+    cRejCbZero,
+    cRejCbMetro,
+    cDrawn,
+    cResolved,
+    cCbTrials,
+    cOverlapChecks,
+    cNearContact,
+    cFp64Fallbacks,
+};
+
+enum Flags : int { kFlagListOverflow = 1, kFlagOwnOverflow = 2 };
+
+// constants of one state point, passed by value to every kernel
+struct Params {
+    Shape S;
+    int N;
+    int n;      // cells per axis (even)
+    int h;      // n / 2
+    int ncells; // n^3
+    int n_select;
+    int n_trial;
+    int n_chunks;
+    int has_dep;
+    int trace;
+    int precision;
+    uint32_t key0, key1;
+    uint32_t sweep;
+    double L, halfL, w, inv_w;
+    double d_trans, a_rot, p_rot;
+    double s_ball;  // R0 * 2^-21
+    // per-wave LDS layout of the phase kernel
+    int list_cap, own_cap, geo_cap;
+    int wave_lds;       // bytes per wave
+    int off_own_pos, off_own_q, off_geo;
+    int waves_per_block;
+    int active_cells;   // h^3
+};
+
+// device workspace carved from the caller's buffer
+struct Work {
+    int* cell_count;   // ncells
+    int* cell_start;   // ncells + 1
+    int* scan_tmp;     // scan block totals
+    int* pcell;        // N
+    int* prank;        // N
+    int* order;        // N: sorted slot -> particle
+    double4* rpos;     // N: cell-ordered (x, y, z, particle index)
+    double4* rquat;    // N: cell-ordered (w, x, y, z) (oriented shapes)
+    double* F;         // kPoissonK
+    double* grid;      // shift g[3]
+    int* perm;         // colour order [8]
+    unsigned long long* counters;  // kCounterCopies x kCounterStride
+    void* trace;       // hpmc_move_record[N * n_select] or null
+    int* flags;
+    unsigned long long* obs;  // observables scratch
+};
+
+struct StateRef {
+    double* pos;   // [3][N]
+    double* quat;  // [4][N] or null
+};
+
+// host-side launchers (enqueue on `stream`)
+hipError_t launch_fill_int(int* p, int n, int value, hipStream_t stream);
+hipError_t launch_fill_u64(unsigned long long* p, int n, hipStream_t stream);
+hipError_t launch_build_cells(const Params& P, const Work& W, const StateRef& st, bool with_grid, hipStream_t stream);
+hipError_t launch_phase(const Params& P, const Work& W, int phase, hipStream_t stream);
+hipError_t launch_scatter_back(const Params& P, const Work& W, const StateRef& st, hipStream_t stream);
+hipError_t launch_overlap_count(const Params& P, const Work& W, hipStream_t stream);
+hipError_t launch_reduce_counters(const Work& W, hipStream_t stream);
+hipError_t launch_gr(const Params& P, const Work& W, int n_bins, double r_max, hipStream_t stream);
+hipError_t launch_free_volume(const Params& P, const Work& W, int64_t n_probe, uint32_t seq, double scale,
+                              int slot, hipStream_t stream);
+hipError_t launch_sdf(const Params& P, const Work& W, int n_bins, double x_max, hipStream_t stream);
+
+}  // namespace hpmc

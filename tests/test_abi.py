@@ -1,0 +1,125 @@
+"""The C-ABI library loads on the host and exports every entry point that
+include/hpmc.h declares; host-only argument validation works without a GPU
+(no device work is launched here)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hpmc.h")
+
+
+@pytest.fixture(scope="module")
+def hp():
+    import paper_1508_07077_amd as hp
+
+    if not os.path.exists(hp.LIB_PATH):
+        from paper_1508_07077_amd import build
+
+        build.build()
+    return hp
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hpmc_[a-z_]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree(hp):
+    assert _declared() == sorted(hp.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(hp):
+    out = subprocess.run(["nm", "-D", "--defined-only", hp.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    syms = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    missing = [s for s in _declared() if s not in syms]
+    assert not missing, missing
+    L = hp.lib()
+    for s in _declared():
+        assert getattr(L, s) is not None
+
+
+def _handle(hp, n=64, L=6.9459):
+    h = ctypes.c_void_p()
+    assert hp.lib().hpmc_create(ctypes.byref(h), n, L, 1, 0, 0, None) == 0
+    return h
+
+
+def _dp(a):
+    return np.ascontiguousarray(a, dtype=np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def test_create_validation(hp):
+    L = hp.lib()
+    h = ctypes.c_void_p()
+    assert L.hpmc_create(ctypes.byref(h), 0, 5.0, 1, 0, 0, None) == -1
+    assert L.hpmc_create(ctypes.byref(h), 10, -5.0, 1, 0, 0, None) == -1
+    assert L.hpmc_create(ctypes.byref(h), 10, 5.0, 1, 0, 7, None) == -1
+    assert L.hpmc_create(None, 10, 5.0, 1, 0, 0, None) == -1
+
+
+def test_parameter_validation_and_errors(hp):
+    L = hp.lib()
+    h = _handle(hp)
+    b = ctypes.c_size_t()
+    assert L.hpmc_workspace_bytes(h, ctypes.byref(b)) == -5  # no shape yet
+    assert L.hpmc_set_shape(h, 9, _dp([1.0]), 1) == -1
+    assert L.hpmc_set_shape(h, 0, _dp([-1.0]), 1) == -1
+    assert L.hpmc_set_shape(h, 2, _dp([0.5]), 1) == -1  # discoid needs two radii
+    assert L.hpmc_set_shape(h, 0, _dp([1.0]), 1) == 0
+    assert L.hpmc_set_fugacity(h, -1.0, 0.25, 0) == -1
+    assert b"invalid" in L.hpmc_last_error(h)
+    assert L.hpmc_set_fugacity(h, 12.0, 0.25, 300) == -1
+    assert L.hpmc_set_fugacity(h, 12.0, 0.25, 4) == 0
+    assert L.hpmc_set_moves(h, -0.1, 0.0, 0.0, 1) == -1
+    assert L.hpmc_set_moves(h, 0.1, 0.0, 1.5, 1) == -1
+    assert L.hpmc_set_moves(h, 0.1, 0.0, 0.0, 0) == -1
+    assert L.hpmc_set_moves(h, 0.1, 0.0, 0.0, 1) == 0
+    assert L.hpmc_workspace_bytes(h, ctypes.byref(b)) == 0 and b.value > 0
+    # no workspace / state: calls that would touch the device refuse first
+    c = hp._Counters()
+    assert L.hpmc_sweep(h, 1, ctypes.byref(c)) == -5
+    assert L.hpmc_set_workspace(h, None, 0) == -1
+    assert L.hpmc_set_workspace(h, ctypes.c_void_p(1 << 20), 16) == -4
+    sw = ctypes.c_uint64()
+    assert L.hpmc_get_state(h, ctypes.byref(sw)) == -5
+    n = ctypes.c_int64()
+    assert L.hpmc_trace(h, None, 0, ctypes.byref(n)) == -5
+    L.hpmc_destroy(h)
+
+
+def test_box_too_small(hp):
+    L = hp.lib()
+    h = _handle(hp, n=4, L=1.9)
+    assert L.hpmc_set_shape(h, 0, _dp([1.0]), 1) == -2  # 2 cells of width >= d do not fit
+    h2 = _handle(hp, n=4, L=2.2)
+    assert L.hpmc_set_shape(h2, 0, _dp([1.0]), 1) == 0
+    assert L.hpmc_set_fugacity(h2, 10.0, 0.25, 0) == -2  # width 1.25 no longer fits twice
+    L.hpmc_destroy(h2)
+    L.hpmc_destroy(h)
+
+
+def test_workspace_grows_with_trace(hp):
+    L = hp.lib()
+    h = _handle(hp)
+    assert L.hpmc_set_shape(h, 0, _dp([1.0]), 1) == 0
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    L.hpmc_workspace_bytes(h, ctypes.byref(a))
+    assert L.hpmc_set_trace(h, 1) == 0
+    L.hpmc_workspace_bytes(h, ctypes.byref(b))
+    assert b.value >= a.value + 64 * 40
+    L.hpmc_destroy(h)
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    import paper_1508_07077_amd as hp
+
+    monkeypatch.setattr(hp, "LIB_PATH", "/nonexistent/libhpmc.so")
+    monkeypatch.setattr(hp, "_lib", None)
+    with pytest.raises(ImportError):
+        hp.lib()
