@@ -874,13 +874,14 @@ static int trial(orc_sim* s, int64_t j, const double xn[3], const double qn[4], 
             }
             /* configurational bias (Sec. III.D): forward re-insertions into B(x, R0)
              * that are valid in M' and overlap the old pose */
+            /* trial i is the i-th accepted candidate of the stream of depletant k */
             uint32_t Wf = 0;
+            ball_stream_t fs;
+            ball_stream_init(&fs, st, P_CB_FWD, k << 16);
             for (int i = 0; i < s->n_trial; ++i) {
-                ball_stream_t fs;
-                ball_stream_init(&fs, st, P_CB_FWD, (k << 16) | ((uint32_t)i << 8));
                 int32_t mf[3];
                 double f[3] = {0, 0, 0}, p[3];
-                if (ball_stream_next(&fs, mf, 256)) {
+                if (ball_stream_next(&fs, mf, 65536)) {
                     f[0] = s->s_ball * (double)mf[0];
                     f[1] = s->s_ball * (double)mf[1];
                     f[2] = s->s_ball * (double)mf[2];
@@ -901,12 +902,12 @@ static int trial(orc_sim* s, int64_t j, const double xn[3], const double qn[4], 
             }
             /* reverse: n_trial - 1 insertions into B(x', R0), valid in M, overlapping the new pose */
             uint32_t Wr = 0;
+            ball_stream_t rs;
+            ball_stream_init(&rs, st, P_CB_REV, k << 16);
             for (int i = 0; i < s->n_trial - 1; ++i) {
-                ball_stream_t rs;
-                ball_stream_init(&rs, st, P_CB_REV, (k << 16) | ((uint32_t)i << 8));
                 int32_t mr[3];
                 double r[3] = {0, 0, 0};
-                if (ball_stream_next(&rs, mr, 256)) {
+                if (ball_stream_next(&rs, mr, 65536)) {
                     r[0] = s->s_ball * (double)mr[0];
                     r[1] = s->s_ball * (double)mr[1];
                     r[2] = s->s_ball * (double)mr[2];
