@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--n", type=int, default=1048576)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle CPU-baseline budget (0 disables)")
     ap.add_argument("--cpu-n", type=int, default=40000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy (scales the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -101,6 +103,15 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_each_way": src.numel() * 8, "copies": 3}))
+        return
 
     import paper_1508_07077_amd as hp
     from paper_1508_07077_amd import workloads as wl

@@ -41,6 +41,7 @@ struct hpmc_sim {
     double w = 0, inv_w = 0, R0 = 0, lambda = 0, lambda_c = 0, s_ball = 0;
     int n_chunks = 1;
     double F[kPoissonK];
+    int G[kGuide];  // guide: first k with F[k] >= i / kGuide
     int F_dirty = 1;
     // state and workspace
     double* pos = nullptr;
@@ -104,6 +105,11 @@ int derive(hpmc_sim* s)
         s->F[k] = s->F[k - 1] + P;
     }
     s->F[kPoissonK - 1] = 2.0;
+    for (int i = 0, k = 0; i < kGuide; ++i) {
+        double lev = static_cast<double>(i) / static_cast<double>(kGuide);
+        while (s->F[k] < lev) ++k;
+        s->G[i] = k;
+    }
     s->F_dirty = 1;
     Shape& S = s->S;
     S.r_dep = r_dep;
@@ -139,7 +145,7 @@ Layout layout(const hpmc_sim* s)
     l.order = take(N * 4);
     l.rpos = take(N * 32);
     l.rquat = take(s->S.oriented ? N * 32 : 0);
-    l.F = take(kPoissonK * 8);
+    l.F = take(kPoissonK * 8 + kGuide * 4);
     l.grid = take(4 * 8);
     l.perm = take(8 * 4);
     l.counters = take(static_cast<size_t>(kCounterCopies) * kCounterStride * 8);
@@ -225,7 +231,7 @@ Params make_params(const hpmc_sim* s)
     off = align256(off + static_cast<size_t>(geo_cap) * 8 * gs);
     P.wave_lds = static_cast<int>(off);
     int wpb = 4;
-    while (wpb > 1 && kPoissonK * 8 + static_cast<size_t>(wpb) * off > 64 * 1024) wpb >>= 1;
+    while (wpb > 1 && kTableLds + static_cast<size_t>(wpb) * off > 64 * 1024) wpb >>= 1;
     P.waves_per_block = wpb;
     return P;
 }
@@ -239,7 +245,7 @@ int check_ready(hpmc_sim* s, bool need_state)
     if (s->ws_bytes < layout(s).total) return fail(s, HPMC_ENOMEM, "workspace too small for the current settings");
     if (need_state && !s->have_state) return fail(s, HPMC_ESTATE, "state not set");
     Params P = make_params(s);
-    if (kPoissonK * 8 + static_cast<size_t>(P.waves_per_block) * P.wave_lds > 64 * 1024)
+    if (kTableLds + static_cast<size_t>(P.waves_per_block) * P.wave_lds > 64 * 1024)
         return fail(s, HPMC_ECAPACITY, "stencil too large for the LDS of one workgroup");
     return HPMC_OK;
 }
@@ -248,6 +254,8 @@ int upload_table(hpmc_sim* s)
 {
     if (!s->F_dirty) return HPMC_OK;
     hipError_t e = hipMemcpyAsync(s->W.F, s->F, sizeof(s->F), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->W.F + kPoissonK, s->G, sizeof(s->G), hipMemcpyHostToDevice, s->stream);
     if (e != hipSuccess) return hip_fail(s, e, "hipMemcpyAsync(table)");
     s->F_dirty = 0;
     return HPMC_OK;

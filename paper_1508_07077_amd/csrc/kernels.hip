@@ -106,20 +106,6 @@ __device__ inline Words draw(const Params& P, uint32_t cell, uint32_t t, uint32_
     return philox(P.sweep, cell, (t << 8) | purpose, index, P.key0, P.key1);
 }
 
-// smallest k with F[k] >= u (F nondecreasing, F[kPoissonK-1] is a sentinel)
-__device__ inline int poisson_search(const double* F, double u)
-{
-    int lo = 0, hi = kPoissonK - 1;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (F[mid] >= u)
-            hi = mid;
-        else
-            lo = mid + 1;
-    }
-    return lo;
-}
-
 // 4-ball candidate: 25-bit fields, odd m in (-2^25, 2^25), accepted iff sum m^2 < 2^50
 __device__ inline bool ball4(Words w, double m[4])
 {
@@ -214,28 +200,65 @@ __device__ inline bool stencil_hit_lane(const Params& P, const Work& W, const Wa
     return hit && active;
 }
 
-// first accepted ball candidate of a CB sub-stream (at most 256 blocks),
-// lanes loop together until every active lane has its point
-__device__ inline Vec3 cb_point(const Params& P, uint32_t cell, uint32_t t, uint32_t purpose, uint32_t index_base,
-                                bool active)
+// CB trial insertions of blocking depletant ks (Sec. III.D): forward trial i is
+// the i-th accepted ball candidate of the CB_FWD stream of ks (uniform in
+// B(x, R0)), reverse trial i the i-th of the CB_REV stream (uniform in
+// B(x', R0)).  Lanes 0-31 draw forward blocks, lanes 32-63 reverse blocks; a
+// ballot rank inside each half assigns the trial index, so one Philox pass
+// usually yields every trial.  Returns the valid counts W'_k and W_k.
+template <int KIND>
+__device__ inline void cb_weights(const Params& P, const Work& W, const WaveCtx& c, uint32_t C, uint32_t t,
+                                  uint32_t ks, Vec3 Dold, const Mat3& Rn, const Mat3& Ro, uint32_t& Wf, uint32_t& Wr)
 {
-    bool found = !active;
-    Vec3 f = v3(0.0, 0.0, 0.0);
-    for (uint32_t b = 0; b < 256u; ++b) {
-        if (!found) {
-            Words w = draw(P, cell, t, purpose, index_base + b);
-            double m0, m1, m2;
-            if (ball3(w.w0, w.w1, m0, m1, m2)) {
-                f = v3(P.s_ball * m0, P.s_ball * m1, P.s_ball * m2);
-                found = true;
-            } else if (ball3(w.w2, w.w3, m0, m1, m2)) {
-                f = v3(P.s_ball * m0, P.s_ball * m1, P.s_ball * m2);
-                found = true;
-            }
+    const int lane = lane_id();
+    const bool fwd = lane < 32;
+    const unsigned long long lo_half = 0x00000000FFFFFFFFull;
+    const unsigned long long half = fwd ? lo_half : ~lo_half;
+    const int need_f = P.n_trial, need_r = P.n_trial - 1;
+    int have_f = 0, have_r = 0;
+    Wf = 0;
+    Wr = 0;
+    for (uint32_t blk = 0; (have_f < need_f || have_r < need_r) && blk < 65536u; blk += 32) {
+        const int have = fwd ? have_f : have_r;
+        const int need = fwd ? need_f : need_r;
+        Words w = draw(P, C, t, fwd ? kCbFwd : kCbRev, (ks << 16) | (blk + static_cast<uint32_t>(lane & 31)));
+        double a0, a1, a2, b0, b1, b2;
+        bool c0 = ball3(w.w0, w.w1, a0, a1, a2) && have < need;
+        bool c1 = ball3(w.w2, w.w3, b0, b1, b2) && have < need;
+        const unsigned long long M0 = __ballot(c0), M1 = __ballot(c1);
+        int r0 = have + bits_below(M0 & half) + bits_below(M1 & half);
+        int r1 = r0 + (c0 ? 1 : 0);
+        bool v0 = c0 && r0 < need, v1 = c1 && r1 < need;
+        Vec3 f0 = v3(P.s_ball * a0, P.s_ball * a1, P.s_ball * a2);
+        Vec3 f1 = v3(P.s_ball * b0, P.s_ball * b1, P.s_ball * b2);
+        // forward: overlaps the old pose (implied for spheres), misses the new pose;
+        // reverse: overlaps the new pose (implied for spheres), misses the old pose
+        Vec3 p0 = fwd ? (Dold + f0) : f0, p1 = fwd ? (Dold + f1) : f1;
+        if (v0) {
+            if constexpr (Traits<KIND>::oriented) v0 = dep_ov<KIND>(P.S, f0, fwd ? Ro : Rn);
+            if (v0) v0 = fwd ? !dep_ov<KIND>(P.S, p0, Rn) : !dep_ov<KIND>(P.S, f0 - Dold, Ro);
         }
-        if (__ballot(!found) == 0ull) break;
+        if (v1) {
+            if constexpr (Traits<KIND>::oriented) v1 = dep_ov<KIND>(P.S, f1, fwd ? Ro : Rn);
+            if (v1) v1 = fwd ? !dep_ov<KIND>(P.S, p1, Rn) : !dep_ov<KIND>(P.S, f1 - Dold, Ro);
+        }
+        // and miss every other colloid of the stencil
+        v0 = v0 && !stencil_hit_lane<KIND>(P, W, c, p0, v0);
+        v1 = v1 && !stencil_hit_lane<KIND>(P, W, c, p1, v1);
+        const unsigned long long V0 = __ballot(v0), V1 = __ballot(v1);
+        Wf += static_cast<uint32_t>(__popcll(V0 & lo_half) + __popcll(V1 & lo_half));
+        Wr += static_cast<uint32_t>(__popcll(V0 & ~lo_half) + __popcll(V1 & ~lo_half));
+        have_f += __popcll(M0 & lo_half) + __popcll(M1 & lo_half);
+        have_r += __popcll(M0 & ~lo_half) + __popcll(M1 & ~lo_half);
     }
-    return f;
+}
+
+// smallest k with F[k] >= u, starting from the guide entry G[floor(256 u)]
+__device__ inline int poisson_guided(const double* F, const int* G, double u)
+{
+    int k = G[static_cast<int>(u * 256.0)];
+    while (F[k] < u) ++k;
+    return k;
 }
 
 struct TrialOut {
@@ -413,16 +436,19 @@ __global__ void scatter_back_kernel(Params P, Work W, double* __restrict__ pos, 
 // one colour of the checkerboard: every active cell runs its trials
 // ---------------------------------------------------------------------------
 template <int KIND>
-__global__ __launch_bounds__(256) void phase_kernel(Params P, Work W, int phase)
+__device__ __forceinline__ void phase_body(const Params& P, const Work& W, int phase)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     double* sF = reinterpret_cast<double*>(smem);
+    int* sG = reinterpret_cast<int*>(smem + kPoissonK * sizeof(double));
+    const int* gG = reinterpret_cast<const int*>(W.F + kPoissonK);
     for (int i = threadIdx.x; i < kPoissonK; i += blockDim.x) sF[i] = W.F[i];
+    for (int i = threadIdx.x; i < kGuide; i += blockDim.x) sG[i] = gG[i];
     __syncthreads();
 
     const int lane = lane_id();
     const int wv = threadIdx.x >> 6;
-    unsigned char* wbase = smem + kPoissonK * sizeof(double) + static_cast<size_t>(wv) * P.wave_lds;
+    unsigned char* wbase = smem + kTableLds + static_cast<size_t>(wv) * P.wave_lds;
     WaveCtx c;
     c.list = reinterpret_cast<int*>(wbase);
     c.own_pos = reinterpret_cast<double4*>(wbase + P.off_own_pos);
@@ -569,11 +595,18 @@ __global__ __launch_bounds__(256) void phase_kernel(Params P, Work W, int phase)
                 o.reason = 1;
             } else {
                 // --- geometry cache of the stencil relative to x' ----------------
+                // (lane i also keeps entry i in registers for the survivor tests)
                 const int ng = c.nst < P.geo_cap ? c.nst : P.geo_cap;
+                Vec3 Dreg = v3(kFar, kFar, kFar);
+                if (lane < c.nst && lane >= ng) {
+                    Mat3 R;
+                    load_entry<KIND>(P, W, c, lane, Dreg, R);
+                }
                 for (int i = lane; i < ng; i += 64) {
                     Vec3 D;
                     Mat3 R;
                     load_entry<KIND>(P, W, c, i, D, R);
+                    if (i == lane) Dreg = D;
                     double* g = c.geo + static_cast<size_t>(i) * GS;
                     g[0] = D.x;
                     g[1] = D.y;
@@ -608,13 +641,13 @@ __global__ __launch_bounds__(256) void phase_kernel(Params P, Work W, int phase)
                 } else if (P.has_dep) {
                     // --- Poisson number of depletants in V_0 = B(x', R0) ----------
                     int kc = 0;
-                    if (lane >= 3 && lane < 32 && lane - 3 < P.n_chunks) kc = poisson_search(sF, u52(w.w0, w.w1));
+                    if (lane >= 3 && lane < 32 && lane - 3 < P.n_chunks) kc = poisson_guided(sF, sG, u52(w.w0, w.w1));
                     for (int base = 29; base < P.n_chunks; base += 64) {
                         int ci = base + lane;
                         if (ci < P.n_chunks) {
                             Words pw = draw(P, static_cast<uint32_t>(C), static_cast<uint32_t>(t), kPoisson,
                                             static_cast<uint32_t>(ci));
-                            kc += poisson_search(sF, u52(pw.w0, pw.w1));
+                            kc += poisson_guided(sF, sG, u52(pw.w0, pw.w1));
                         }
                     }
                     const uint32_t Np = static_cast<uint32_t>(wave_sum(kc));
@@ -663,7 +696,20 @@ __global__ __launch_bounds__(256) void phase_kernel(Params P, Work W, int phase)
                             Vec3 es = cand ? e1 : e0;
                             es = v3(rdlane_d(es.x, src), rdlane_d(es.y, src), rdlane_d(es.z, src));
                             uint32_t ks = rdlane_u(cand ? k1 : k0, src);
-                            if (stencil_hit_coop<KIND>(P, W, c, es)) continue;  // ignored
+                            bool ignored;
+                            if constexpr (!ORI) {
+                                bool h = dep_ov<KIND>(P.S, es - Dreg, Rn);
+                                for (int i = 64 + lane; i < c.nst; i += 64) {
+                                    Vec3 D;
+                                    Mat3 R;
+                                    get_entry<KIND>(P, W, c, i, D, R);
+                                    h = h || dep_ov<KIND>(P.S, es - D, R);
+                                }
+                                ignored = __ballot(h) != 0ull;
+                            } else {
+                                ignored = stencil_hit_coop<KIND>(P, W, c, es);
+                            }
+                            if (ignored) continue;
                             // blocking: free in M, overlapping M'
                             o.nblk++;
                             if (P.n_trial == 0) {
@@ -674,30 +720,9 @@ __global__ __launch_bounds__(256) void phase_kernel(Params P, Work W, int phase)
                             }
                             // configurational bias: n_trial forward + (n_trial - 1) reverse insertions
                             const int ntot = 2 * P.n_trial - 1;
-                            uint32_t Wf = 0, Wr = 0;
-                            for (int base = 0; base < ntot; base += 64) {
-                                int idx = base + lane;
-                                bool active = idx < ntot;
-                                bool fwd = idx < P.n_trial;
-                                int ti = fwd ? idx : idx - P.n_trial;
-                                uint32_t ib = (ks << 16) | (static_cast<uint32_t>(ti) << 8);
-                                Vec3 f = cb_point(P, static_cast<uint32_t>(C), static_cast<uint32_t>(t),
-                                                  fwd ? kCbFwd : kCbRev, ib, active);
-                                bool valid = active;
-                                Vec3 pt = fwd ? (Dold + f) : f;
-                                if (valid) {
-                                    if (fwd) {
-                                        if constexpr (ORI) valid = dep_ov<KIND>(P.S, f, Ro);
-                                        if (valid) valid = !dep_ov<KIND>(P.S, pt, Rn);
-                                    } else {
-                                        if constexpr (ORI) valid = dep_ov<KIND>(P.S, f, Rn);
-                                        if (valid) valid = !dep_ov<KIND>(P.S, f - Dold, Ro);
-                                    }
-                                }
-                                valid = valid && !stencil_hit_lane<KIND>(P, W, c, pt, valid);
-                                Wf += static_cast<uint32_t>(__popcll(__ballot(valid && fwd)));
-                                Wr += static_cast<uint32_t>(__popcll(__ballot(valid && !fwd)));
-                            }
+                            uint32_t Wf, Wr;
+                            cb_weights<KIND>(P, W, c, static_cast<uint32_t>(C), static_cast<uint32_t>(t), ks, Dold, Rn,
+                                             Ro, Wf, Wr);
                             o.wf += Wf;
                             if (Wf == 0) {
                                 o.reason = 4;
@@ -768,6 +793,23 @@ __global__ __launch_bounds__(256) void phase_kernel(Params P, Work W, int phase)
         for (int k = 0; k < kNumCounters; ++k)
             if (cnt[k]) atomicAdd(dst + k, cnt[k]);
     }
+}
+
+// Spheres: registers capped for HPMC_SPHERE_WAVES_PER_EU waves per SIMD (the
+// depletant loop is issue-bound, more waves hide the LDS and memory latency).
+#ifndef HPMC_SPHERE_WAVES_PER_EU
+#define HPMC_SPHERE_WAVES_PER_EU 3
+#endif
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HPMC_SPHERE_WAVES_PER_EU, 8))) void
+phase_sphere_kernel(Params P, Work W, int phase)
+{
+    phase_body<kSphere>(P, W, phase);
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256) void phase_oriented_kernel(Params P, Work W, int phase)
+{
+    phase_body<KIND>(P, W, phase);
 }
 
 __global__ void reduce_counters_kernel(Work W)
@@ -1027,18 +1069,18 @@ hipError_t launch_build_cells(const Params& P, const Work& W, const StateRef& st
 
 hipError_t launch_phase(const Params& P, const Work& W, int phase, hipStream_t stream)
 {
-    size_t lds = kPoissonK * sizeof(double) + static_cast<size_t>(P.waves_per_block) * P.wave_lds;
+    size_t lds = kTableLds + static_cast<size_t>(P.waves_per_block) * P.wave_lds;
     int waves = P.active_cells;
     int max_waves = 256 * 32;
     if (waves > max_waves) waves = max_waves;
     int blocks = blocks_for(waves, P.waves_per_block);
     dim3 bs(64 * P.waves_per_block);
     switch (P.S.kind) {
-    case kSphere: hipLaunchKernelGGL(phase_kernel<kSphere>, dim3(blocks), bs, lds, stream, P, W, phase); break;
+    case kSphere: hipLaunchKernelGGL(phase_sphere_kernel, dim3(blocks), bs, lds, stream, P, W, phase); break;
     case kHemisphere:
-        hipLaunchKernelGGL(phase_kernel<kHemisphere>, dim3(blocks), bs, lds, stream, P, W, phase);
+        hipLaunchKernelGGL(phase_oriented_kernel<kHemisphere>, dim3(blocks), bs, lds, stream, P, W, phase);
         break;
-    default: hipLaunchKernelGGL(phase_kernel<kDiscoid>, dim3(blocks), bs, lds, stream, P, W, phase); break;
+    default: hipLaunchKernelGGL(phase_oriented_kernel<kDiscoid>, dim3(blocks), bs, lds, stream, P, W, phase); break;
     }
     return hipGetLastError();
 }

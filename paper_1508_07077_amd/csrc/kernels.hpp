@@ -10,6 +10,8 @@
 namespace hpmc {
 
 constexpr int kPoissonK = 1024;      // inverse-CDF table length (last entry is a sentinel)
+constexpr int kGuide = 256;          // guide table: first k with F[k] >= i / 256
+constexpr int kTableLds = kPoissonK * 8 + kGuide * 4;
 constexpr int kCounterCopies = 256;  // spread copies of the counters (atomic contention)
 constexpr int kNumCounters = 13;
 constexpr int kCounterStride = 16;
@@ -68,7 +70,7 @@ struct Work {
     int* order;        // N: sorted slot -> particle
     double4* rpos;     // N: cell-ordered (x, y, z, particle index)
     double4* rquat;    // N: cell-ordered (w, x, y, z) (oriented shapes)
-    double* F;         // kPoissonK
+    double* F;         // kPoissonK doubles, then kGuide ints
     double* grid;      // shift g[3]
     int* perm;         // colour order [8]
     unsigned long long* counters;  // kCounterCopies x kCounterStride

@@ -93,7 +93,8 @@ __host__ __device__ inline bool ball3(uint32_t wa, uint32_t wb, double& m0, doub
     m0 = static_cast<double>(static_cast<int32_t>(2u * f0 + 1u) - (1 << 21));
     m1 = static_cast<double>(static_cast<int32_t>(2u * f1 + 1u) - (1 << 21));
     m2 = static_cast<double>(static_cast<int32_t>(2u * f2 + 1u) - (1 << 21));
-    double s = (m0 * m0 + m1 * m1) + m2 * m2;
+    // every partial sum is an integer below 2^44: the fused form is exact
+    double s = fma(m0, m0, fma(m1, m1, m2 * m2));
     return s < 0x1p42;
 }
 

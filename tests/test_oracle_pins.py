@@ -299,3 +299,36 @@ def test_p7_checkpoint_resume_bitwise(oracle):
     p_res, _, sw_res = c.get_state()
     assert sw_full == sw_res == 25
     assert np.array_equal(p_full, p_res)
+
+
+def test_light_cone_sweep_reproduces_full_sweep(oracle):
+    """The restricted sweep used for sampled full-size checks reproduces every
+    record of the cells it targets (C3-shaped box, 14^3 cells)."""
+    from paper_1508_07077_amd import workloads as wl
+
+    sp = wl.c3_spheres_large(n=3000, d_trans=0.02)
+    pos, _ = sp.initial_state()
+
+    def mk():
+        s = oracle.OracleSim(sp.n, sp.L, sp.seed)
+        s.set_shape(oracle.SPHERE, sp.params)
+        s.set_fugacity(sp.z_p, sp.d_dep, sp.n_trial)
+        s.set_moves(sp.d_trans)
+        s.set_trace(True)
+        s.set_state(pos)
+        return s
+
+    full = mk()
+    full.sweep(1)
+    tf = full.trace()
+    assert int(full.derived()["n"]) >= 12
+    rng = np.random.default_rng(1)
+    cells = rng.choice(np.unique(tf["cell"]), 6, replace=False)
+    for c in cells:
+        s = mk()
+        cc = s.sweep_cone(int(c))
+        tc = s.trace()
+        sel = tf["cell"] == c
+        assert np.array_equal(tf[sel], tc[sel])
+        # cells outside the cone were not run
+        assert 0 < cc["trials"] < sp.n
