@@ -222,6 +222,21 @@ Params make_params(const hpmc_sim* s)
     P.list_cap = static_cast<int>(list_cap);
     P.own_cap = static_cast<int>(own_cap);
     P.geo_cap = static_cast<int>(geo_cap);
+    if (!s->S.oriented) {
+        // spheres: two stage buffers, each the stencil list + staged records (x, y) and (z, index)
+        size_t o = align256(static_cast<size_t>(list_cap) * 4);
+        P.off_own_pos = static_cast<int>(o);
+        o = align256(o + 64 * 16);
+        P.off_own_q = static_cast<int>(o);
+        o = align256(o + 64 * 16);
+        P.off_geo = 0;
+        P.wave_lds = static_cast<int>(2 * o);
+        P.own_cap = 64;
+        int wpb = 4;
+        while (wpb > 1 && kTableLds + static_cast<size_t>(wpb) * P.wave_lds > 64 * 1024) wpb >>= 1;
+        P.waves_per_block = wpb;
+        return P;
+    }
     size_t off = align256(static_cast<size_t>(list_cap) * 4);
     P.off_own_pos = static_cast<int>(off);
     off = align256(off + static_cast<size_t>(own_cap) * 32);

@@ -795,15 +795,384 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
     }
 }
 
-// Spheres: registers capped for HPMC_SPHERE_WAVES_PER_EU waves per SIMD (the
-// depletant loop is issue-bound, more waves hide the LDS and memory latency).
+// ---------------------------------------------------------------------------
+// Spheres: one wave per chunk of kChunk active cells.  The stencil records of
+// a cell (its own members first, then the 26 neighbour cells) are staged in
+// LDS by direct global->LDS loads issued while the previous non-empty cell of
+// the chunk runs its trials; neighbour ranges two cells ahead are loaded into
+// registers at the same time.  Trials then read only LDS and registers.
+// ---------------------------------------------------------------------------
+constexpr int kChunk = 16;
+constexpr int kStage = 64;  // staged stencil entries per cell (more are read from HBM)
+
+struct SphereStage {
+    int* list;      // stencil slots (list_cap)
+    double* recA;   // entry i: (x, y) at [2i, 2i + 1]
+    double* recB;   // entry i: (z, particle index) at [2i, 2i + 1]
+};
+
+__device__ inline double4 stage_rec(const SphereStage& sb, int i)
+{
+    return make_double4(sb.recA[2 * i], sb.recA[2 * i + 1], sb.recB[2 * i], sb.recB[2 * i + 1]);
+}
+
+// neighbour-cell ranges of cell C (lane l < ncl holds the range of neighbour l;
+// neighbour 0 is C itself)
+__device__ inline void stencil_ranges(const Params& P, const Work& W, int C, int& es, int& ec)
+{
+    const int lane = lane_id();
+    const int noff = (P.n == 2) ? 2 : 3;
+    const int ncl = noff * noff * noff;
+    es = 0;
+    ec = 0;
+    if (C >= 0 && lane < ncl) {
+        // offsets ordered 0, -1, +1 (n > 2) or 0, +1 (n = 2): neighbour 0 is the cell itself
+        int ix = lane % noff, iy = (lane / noff) % noff, iz = lane / (noff * noff);
+        int dx = (noff == 3 && ix == 1) ? -1 : (ix == 2 ? 1 : ix);
+        int dy = (noff == 3 && iy == 1) ? -1 : (iy == 2 ? 1 : iy);
+        int dz = (noff == 3 && iz == 1) ? -1 : (iz == 2 ? 1 : iz);
+        int cx = C % P.n, cy = (C / P.n) % P.n, cz = C / (P.n * P.n);
+        int e = (cx + dx + P.n) % P.n + P.n * ((cy + dy + P.n) % P.n + P.n * ((cz + dz + P.n) % P.n));
+        es = W.cell_start[e];
+        ec = W.cell_start[e + 1] - es;
+    }
+}
+
+// write the stencil list of a cell and start the direct loads of its first
+// kStage records into LDS; returns the stencil size (or -1 on overflow)
+__device__ inline int stage_issue(const Params& P, const Work& W, const SphereStage& sb, int es, int ec)
+{
+    const int lane = lane_id();
+    int nst;
+    int off = wave_excl_scan(ec, nst);
+    if (nst > P.list_cap) return -1;
+    for (int k = 0; k < ec; ++k) sb.list[off + k] = es + k;
+    wave_sync();
+    if (lane < nst && lane < kStage) {
+        const char* g = reinterpret_cast<const char*>(W.rpos + sb.list[lane]);
+        __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)(sb.recA), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(g + 16, (__attribute__((address_space(3))) void*)(sb.recB), 16, 0, 0);
+    }
+    return nst;
+}
+
+// does a point at offset p (from x') overlap any stencil colloid?  per lane,
+// entries read from LDS (all lanes read the same entry: broadcast)
+__device__ inline bool sphere_hit_lane(const Params& P, const Work& W, const SphereStage& sb, int nst, int jent,
+                                       Vec3 xn, Vec3 p, bool active)
+{
+    bool hit = !active;
+    for (int i = 0; i < nst; ++i) {
+        if (__ballot(!hit) == 0ull) break;
+        if (i == jent) continue;
+        double4 r = (i < kStage) ? stage_rec(sb, i) : W.rpos[sb.list[i]];
+        Vec3 D = v3(mi(P, r.x - xn.x), mi(P, r.y - xn.y), mi(P, r.z - xn.z));
+        if (!hit) hit = dot(p - D, p - D) < P.S.R0sq;
+    }
+    return hit && active;
+}
+
+__device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W, int phase)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    double* sF = reinterpret_cast<double*>(smem);
+    int* sG = reinterpret_cast<int*>(smem + kPoissonK * sizeof(double));
+    const int* gG = reinterpret_cast<const int*>(W.F + kPoissonK);
+    for (int i = threadIdx.x; i < kPoissonK; i += blockDim.x) sF[i] = W.F[i];
+    for (int i = threadIdx.x; i < kGuide; i += blockDim.x) sG[i] = gG[i];
+    __syncthreads();
+
+    const int lane = lane_id();
+    const int wv = threadIdx.x >> 6;
+    unsigned char* wbase = smem + kTableLds + static_cast<size_t>(wv) * P.wave_lds;
+    auto stage_buf = [&](int b) {
+        unsigned char* q = wbase + static_cast<size_t>(b) * (P.wave_lds / 2);
+        return SphereStage{reinterpret_cast<int*>(q), reinterpret_cast<double*>(q + P.off_own_pos),
+                           reinterpret_cast<double*>(q + P.off_own_q)};
+    };
+
+    unsigned long long cnt[kNumCounters];
+#pragma unroll
+    for (int k = 0; k < kNumCounters; ++k) cnt[k] = 0ull;
+
+    const int colour = W.perm[phase];
+    const int gw = blockIdx.x * P.waves_per_block + wv;
+    const double g0 = W.grid[0], g1 = W.grid[1], g2 = W.grid[2];
+    const Mat3 Rnone{};
+
+    // the chunk: lane k < kChunk holds active cell gw * kChunk + k
+    int Ck = -1, startk = 0, nck = 0;
+    {
+        int a = gw * kChunk + lane;
+        if (lane < kChunk && a < P.active_cells) {
+            int ax = a % P.h, ay = (a / P.h) % P.h, az = a / (P.h * P.h);
+            int cx = 2 * ax + (colour & 1), cy = 2 * ay + ((colour >> 1) & 1), cz = 2 * az + ((colour >> 2) & 1);
+            Ck = cx + P.n * (cy + P.n * cz);
+            startk = W.cell_start[Ck];
+            nck = W.cell_start[Ck + 1] - startk;
+        }
+    }
+    unsigned long long todo = __ballot(nck > 0);
+    // pipeline: ranges two cells ahead, records one cell ahead
+    auto next_cell = [&](unsigned long long& m) -> int {
+        if (!m) return -1;
+        int k = ffs64(m);
+        m &= m - 1ull;
+        return k;
+    };
+    unsigned long long rem = todo;
+    int kc = next_cell(rem);   // cell being processed
+    int kn = next_cell(rem);   // next
+    int es, ec;
+    stencil_ranges(P, W, kc >= 0 ? static_cast<int>(rdlane_u(static_cast<uint32_t>(Ck), kc)) : -1, es, ec);
+    int nst_cur = (kc >= 0) ? stage_issue(P, W, stage_buf(0), es, ec) : 0;
+    stencil_ranges(P, W, kn >= 0 ? static_cast<int>(rdlane_u(static_cast<uint32_t>(Ck), kn)) : -1, es, ec);
+    int buf = 0;
+
+    while (kc >= 0) {
+        __builtin_amdgcn_s_waitcnt(0);
+        wave_sync();
+        const SphereStage S0 = stage_buf(buf);
+        const int C = static_cast<int>(rdlane_u(static_cast<uint32_t>(Ck), kc));
+        const int start = static_cast<int>(rdlane_u(static_cast<uint32_t>(startk), kc));
+        const int nc = static_cast<int>(rdlane_u(static_cast<uint32_t>(nck), kc));
+        const int nst = nst_cur;
+        // start staging the next cell while this one runs
+        int kn2 = next_cell(rem);
+        int nst_next = 0;
+        if (kn >= 0) {
+            nst_next = stage_issue(P, W, stage_buf(buf ^ 1), es, ec);
+            stencil_ranges(P, W, kn2 >= 0 ? static_cast<int>(rdlane_u(static_cast<uint32_t>(Ck), kn2)) : -1, es, ec);
+        }
+        if (nst < 0 || nc > kStage) {
+            if (lane == 0) atomicOr(W.flags, kFlagListOverflow);
+        } else {
+            const int ntr = P.n_select * nc;
+            for (int t = 0; t < ntr; ++t) {
+                // --- per-trial draws packed across lanes -----------------------
+                uint32_t purpose = 0, index = 0;
+                if (lane == 0) {
+                    purpose = kSelect;
+                } else if (lane == 1) {
+                    purpose = kTrans;
+                } else if (lane == 2) {
+                    purpose = kAccept;
+                } else {
+                    purpose = kPoisson;
+                    index = static_cast<uint32_t>(lane - 3);
+                }
+                Words w = draw(P, static_cast<uint32_t>(C), static_cast<uint32_t>(t), purpose, index);
+                const int jl = static_cast<int>(pick(rdlane_u(w.w0, 0), static_cast<uint32_t>(nc)));
+                const double4 pj = stage_rec(S0, jl);  // own members are entries 0 .. nc-1
+                Vec3 xn;
+                {
+                    uint32_t tw0 = rdlane_u(w.w0, 1), tw1 = rdlane_u(w.w1, 1), tw2 = rdlane_u(w.w2, 1);
+                    double v;
+                    v = pj.x + P.d_trans * sym01(tw0);
+                    if (v >= P.L) v -= P.L; else if (v < 0.0) v += P.L;
+                    xn.x = v;
+                    v = pj.y + P.d_trans * sym01(tw1);
+                    if (v >= P.L) v -= P.L; else if (v < 0.0) v += P.L;
+                    xn.y = v;
+                    v = pj.z + P.d_trans * sym01(tw2);
+                    if (v >= P.L) v -= P.L; else if (v < 0.0) v += P.L;
+                    xn.z = v;
+                }
+                TrialOut o{0, 0, 0, 0, 0, 0, 0, false};
+                if (cell_of(P, xn.x, xn.y, xn.z, g0, g1, g2) != C) {
+                    o.reason = 1;
+                } else {
+                    // stencil geometry relative to x': lane i holds entry i
+                    Vec3 Dreg = v3(kFar, kFar, kFar);
+                    if (lane < nst && lane < kStage && lane != jl) {
+                        double4 r = stage_rec(S0, lane);
+                        Dreg = v3(mi(P, r.x - xn.x), mi(P, r.y - xn.y), mi(P, r.z - xn.z));
+                    }
+                    // hard overlap with another colloid
+                    bool hit = dot(Dreg, Dreg) < P.S.dsq;
+                    for (int i = kStage + lane; i < nst; i += 64) {
+                        double4 r = W.rpos[S0.list[i]];
+                        Vec3 D = v3(mi(P, r.x - xn.x), mi(P, r.y - xn.y), mi(P, r.z - xn.z));
+                        hit = hit || dot(D, D) < P.S.dsq;
+                    }
+                    cnt[cOverlapChecks] += static_cast<unsigned long long>(nst - 1);
+                    if (__ballot(hit) != 0ull) {
+                        o.reason = 2;
+                    } else if (P.has_dep) {
+                        int kcnt = 0;
+                        if (lane >= 3 && lane - 3 < P.n_chunks) kcnt = poisson_guided(sF, sG, u52(w.w0, w.w1));
+                        for (int base = 61; base < P.n_chunks; base += 64) {
+                            int ci = base + lane;
+                            if (ci < P.n_chunks) {
+                                Words pw = draw(P, static_cast<uint32_t>(C), static_cast<uint32_t>(t), kPoisson,
+                                                static_cast<uint32_t>(ci));
+                                kcnt += poisson_guided(sF, sG, u52(pw.w0, pw.w1));
+                            }
+                        }
+                        const uint32_t Np = static_cast<uint32_t>(wave_sum(kcnt));
+                        o.n_dep = Np;
+                        const double au = u52(rdlane_u(w.w0, 2), rdlane_u(w.w1, 2));
+                        const Vec3 Dold = v3(mi(P, pj.x - xn.x), mi(P, pj.y - xn.y), mi(P, pj.z - xn.z));
+                        double ratio = 1.0;
+                        bool done = false;
+                        uint32_t kbase = 0, blk = 0;
+                        while (!done && kbase < Np && blk < (1u << 30)) {
+                            Words dw = draw(P, static_cast<uint32_t>(C), static_cast<uint32_t>(t), kDepl, blk + lane);
+                            double a0, a1, a2, b0, b1, b2;
+                            bool acc0 = ball3(dw.w0, dw.w1, a0, a1, a2);
+                            bool acc1 = ball3(dw.w2, dw.w3, b0, b1, b2);
+                            unsigned long long m0 = __ballot(acc0), m1 = __ballot(acc1);
+                            uint32_t k0 = kbase + static_cast<uint32_t>(bits_below(m0) + bits_below(m1));
+                            uint32_t k1 = k0 + (acc0 ? 1u : 0u);
+                            Vec3 e0 = v3(P.s_ball * a0, P.s_ball * a1, P.s_ball * a2);
+                            Vec3 e1 = v3(P.s_ball * b0, P.s_ball * b1, P.s_ball * b2);
+                            // ignored by the old pose (every ball point overlaps the new pose)
+                            bool v0 = acc0 && k0 < Np && !(dot(e0 - Dold, e0 - Dold) < P.S.R0sq);
+                            bool v1 = acc1 && k1 < Np && !(dot(e1 - Dold, e1 - Dold) < P.S.R0sq);
+                            unsigned long long r0 = __ballot(v0), r1 = __ballot(v1);
+                            while ((r0 | r1) && !done) {
+                                int l0 = r0 ? ffs64(r0) : 64, l1 = r1 ? ffs64(r1) : 64;
+                                int src, cand;
+                                if (l0 <= l1) {
+                                    src = l0;
+                                    cand = 0;
+                                    r0 &= ~(1ull << l0);
+                                } else {
+                                    src = l1;
+                                    cand = 1;
+                                    r1 &= ~(1ull << l1);
+                                }
+                                src = __builtin_amdgcn_readfirstlane(src);
+                                Vec3 es3 = cand ? e1 : e0;
+                                es3 = v3(rdlane_d(es3.x, src), rdlane_d(es3.y, src), rdlane_d(es3.z, src));
+                                uint32_t ks = rdlane_u(cand ? k1 : k0, src);
+                                bool h = dot(es3 - Dreg, es3 - Dreg) < P.S.R0sq;
+                                for (int i = kStage + lane; i < nst; i += 64) {
+                                    double4 r = W.rpos[S0.list[i]];
+                                    Vec3 D = v3(mi(P, r.x - xn.x), mi(P, r.y - xn.y), mi(P, r.z - xn.z));
+                                    h = h || dot(es3 - D, es3 - D) < P.S.R0sq;
+                                }
+                                if (__ballot(h) != 0ull) continue;  // ignored
+                                o.nblk++;
+                                if (P.n_trial == 0) {
+                                    o.reason = 3;
+                                    o.resolved = ks + 1;
+                                    done = true;
+                                    break;
+                                }
+                                // configurational bias: one ballot-compacted pass per depletant
+                                const unsigned long long lo_half = 0x00000000FFFFFFFFull;
+                                const bool fwd = lane < 32;
+                                const unsigned long long half = fwd ? lo_half : ~lo_half;
+                                const int need_f = P.n_trial, need_r = P.n_trial - 1;
+                                int have_f = 0, have_r = 0;
+                                uint32_t Wf = 0, Wr = 0;
+                                for (uint32_t cb = 0; (have_f < need_f || have_r < need_r) && cb < 65536u; cb += 32) {
+                                    const int have = fwd ? have_f : have_r;
+                                    const int need = fwd ? need_f : need_r;
+                                    Words cw = draw(P, static_cast<uint32_t>(C), static_cast<uint32_t>(t),
+                                                    fwd ? kCbFwd : kCbRev,
+                                                    (ks << 16) | (cb + static_cast<uint32_t>(lane & 31)));
+                                    double c0x, c0y, c0z, c1x, c1y, c1z;
+                                    bool q0 = ball3(cw.w0, cw.w1, c0x, c0y, c0z) && have < need;
+                                    bool q1 = ball3(cw.w2, cw.w3, c1x, c1y, c1z) && have < need;
+                                    const unsigned long long M0 = __ballot(q0), M1 = __ballot(q1);
+                                    int rk0 = have + bits_below(M0 & half) + bits_below(M1 & half);
+                                    int rk1 = rk0 + (q0 ? 1 : 0);
+                                    bool u0 = q0 && rk0 < need, u1 = q1 && rk1 < need;
+                                    Vec3 f0 = v3(P.s_ball * c0x, P.s_ball * c0y, P.s_ball * c0z);
+                                    Vec3 f1 = v3(P.s_ball * c1x, P.s_ball * c1y, P.s_ball * c1z);
+                                    Vec3 p0 = fwd ? (Dold + f0) : f0, p1 = fwd ? (Dold + f1) : f1;
+                                    // forward: misses the new pose; reverse: misses the old pose
+                                    if (u0) u0 = fwd ? !(dot(p0, p0) < P.S.R0sq) : !(dot(f0 - Dold, f0 - Dold) < P.S.R0sq);
+                                    if (u1) u1 = fwd ? !(dot(p1, p1) < P.S.R0sq) : !(dot(f1 - Dold, f1 - Dold) < P.S.R0sq);
+                                    u0 = u0 && !sphere_hit_lane(P, W, S0, nst, jl, xn, p0, u0);
+                                    u1 = u1 && !sphere_hit_lane(P, W, S0, nst, jl, xn, p1, u1);
+                                    const unsigned long long V0 = __ballot(u0), V1 = __ballot(u1);
+                                    Wf += static_cast<uint32_t>(__popcll(V0 & lo_half) + __popcll(V1 & lo_half));
+                                    Wr += static_cast<uint32_t>(__popcll(V0 & ~lo_half) + __popcll(V1 & ~lo_half));
+                                    have_f += __popcll(M0 & lo_half) + __popcll(M1 & lo_half);
+                                    have_r += __popcll(M0 & ~lo_half) + __popcll(M1 & ~lo_half);
+                                }
+                                o.wf += Wf;
+                                if (Wf == 0) {
+                                    o.reason = 4;
+                                    o.resolved = ks + 1 + o.cbt + static_cast<uint32_t>(P.n_trial);
+                                    o.cbt += static_cast<uint32_t>(P.n_trial);
+                                    done = true;
+                                    break;
+                                }
+                                o.wr += Wr;
+                                ratio = ratio * (static_cast<double>(Wf) / static_cast<double>(1 + Wr));
+                                o.cbt += static_cast<uint32_t>(2 * P.n_trial - 1);
+                            }
+                            kbase += static_cast<uint32_t>(__popcll(m0) + __popcll(m1));
+                            blk += 64;
+                        }
+                        if (!done) {
+                            o.resolved = Np + o.cbt;
+                            if (o.nblk > 0 && !(au < ratio)) o.reason = 5;
+                        }
+                    }
+                }
+                // --- accept / commit / record -----------------------------------
+                if (o.reason == 0 && lane == 0) {
+                    S0.recA[2 * jl] = xn.x;
+                    S0.recA[2 * jl + 1] = xn.y;
+                    S0.recB[2 * jl] = xn.z;
+                }
+                wave_sync();
+                cnt[cTrials] += 1;
+                switch (o.reason) {
+                case 0: cnt[cAccepts] += 1; break;
+                case 1: cnt[cRejCellExit] += 1; break;
+                case 2: cnt[cRejOverlap] += 1; break;
+                case 3: cnt[cRejDepletant] += 1; break;
+                case 4: cnt[cRejCbZero] += 1; break;
+                default: cnt[cRejCbMetro] += 1; break;
+                }
+                cnt[cDrawn] += o.n_dep;
+                cnt[cResolved] += o.resolved;
+                cnt[cCbTrials] += o.cbt;
+                if (P.trace && lane == 0) {
+                    uint32_t* r = reinterpret_cast<uint32_t*>(static_cast<unsigned char*>(W.trace) +
+                                                              (static_cast<size_t>(P.n_select) * start + t) * 40);
+                    r[0] = P.sweep;
+                    r[1] = static_cast<uint32_t>(C);
+                    r[2] = static_cast<uint32_t>(t);
+                    r[3] = static_cast<uint32_t>(pj.w);
+                    r[4] = o.n_dep;
+                    r[5] = o.resolved;
+                    r[6] = o.nblk;
+                    r[7] = o.wf;
+                    r[8] = o.wr;
+                    r[9] = static_cast<uint32_t>(phase) | (static_cast<uint32_t>(o.reason) << 8);
+                }
+            }
+            // own-cell records back to HBM
+            for (int i = lane; i < nc; i += 64) W.rpos[start + i] = stage_rec(S0, i);
+        }
+        kc = kn;
+        kn = kn2;
+        nst_cur = nst_next;
+        buf ^= 1;
+    }
+    (void)Rnone;
+    if (lane == 0) {
+        unsigned long long* dst = W.counters + static_cast<size_t>(gw % kCounterCopies) * kCounterStride;
+#pragma unroll
+        for (int k = 0; k < kNumCounters; ++k)
+            if (cnt[k]) atomicAdd(dst + k, cnt[k]);
+    }
+}
+
 #ifndef HPMC_SPHERE_WAVES_PER_EU
 #define HPMC_SPHERE_WAVES_PER_EU 3
 #endif
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HPMC_SPHERE_WAVES_PER_EU, 8))) void
 phase_sphere_kernel(Params P, Work W, int phase)
 {
-    phase_body<kSphere>(P, W, phase);
+    phase_sphere_body(P, W, phase);
 }
 
 template <int KIND>
@@ -1073,6 +1442,7 @@ hipError_t launch_phase(const Params& P, const Work& W, int phase, hipStream_t s
     int waves = P.active_cells;
     int max_waves = 256 * 32;
     if (waves > max_waves) waves = max_waves;
+    if (P.S.kind == kSphere) waves = blocks_for(P.active_cells, kChunk);
     int blocks = blocks_for(waves, P.waves_per_block);
     dim3 bs(64 * P.waves_per_block);
     switch (P.S.kind) {
