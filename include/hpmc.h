@@ -181,6 +181,22 @@ int hpmc_set_trace(hpmc_sim* sim, int enable);
  * Errors: ESTATE, ENOMEM, EHIP, ECAPACITY (checked when out is non-NULL). */
 int hpmc_sweep(hpmc_sim* sim, int n_sweeps, hpmc_counters* out);
 
+/* Device scratch needed by hpmc_sweep_batch for n_sims handles. */
+int hpmc_batch_workspace_bytes(int n_sims, size_t* bytes);
+
+/* Run n_sweeps sweeps of n_sims independent handles (replicas of uneven size,
+ * density and fugacity; growth path of the paper's parallel scheme,
+ * Sec. III.E) in shared launches: every kernel covers all replicas of one
+ * shape kind, indexing them by the grid's second dimension.  Each handle keeps
+ * its own state, workspace and random streams, so every replica's trajectory
+ * is identical to what hpmc_sweep gives it alone.  All handles must be ready
+ * (shape, workspace, state) and use the stream of sims[0]; tracing must be
+ * off.  batch_ws: device scratch of hpmc_batch_workspace_bytes(n_sims).  out:
+ * NULL or n_sims counter records (synchronises).  Errors: EINVAL, ESTATE,
+ * ENOMEM, EHIP, ECAPACITY. */
+int hpmc_sweep_batch(hpmc_sim* const* sims, int n_sims, void* batch_ws, size_t bytes, int n_sweeps,
+                     hpmc_counters* out);
+
 /* Observables of the current state (host out, synchronous):
  *   HPMC_OBS_GR: out[0..n_bins) = g(r) of reference-point distances on
  *     [0, r_max), minimum image;

@@ -45,6 +45,8 @@ EXPORTS = (
     "hpmc_sweep",
     "hpmc_observables",
     "hpmc_trace",
+    "hpmc_batch_workspace_bytes",
+    "hpmc_sweep_batch",
 )
 
 COUNTERS = (
@@ -122,6 +124,8 @@ def lib():
         L.hpmc_sweep.argtypes = [vp, cint, ctypes.POINTER(_Counters)]
         L.hpmc_observables.argtypes = [vp, cint, ctypes.POINTER(_ObsParams), dp, i64]
         L.hpmc_trace.argtypes = [vp, vp, i64, ctypes.POINTER(i64)]
+        L.hpmc_batch_workspace_bytes.argtypes = [cint, ctypes.POINTER(ctypes.c_size_t)]
+        L.hpmc_sweep_batch.argtypes = [ctypes.POINTER(vp), cint, vp, ctypes.c_size_t, cint, ctypes.POINTER(_Counters)]
         for name in EXPORTS:
             if name not in ("hpmc_destroy", "hpmc_last_error"):
                 getattr(L, name).restype = cint
@@ -247,3 +251,32 @@ class Sim:
                                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out_len),
                   "observables")
         return out
+
+
+class Batch:
+    """Several independent handles swept in shared launches (hpmc_sweep_batch)."""
+
+    def __init__(self, sims):
+        import torch
+
+        self.sims = list(sims)
+        self.torch = torch
+        n = len(self.sims)
+        b = ctypes.c_size_t(0)
+        rc = lib().hpmc_batch_workspace_bytes(n, ctypes.byref(b))
+        if rc != 0:
+            raise HpmcError(rc, "hpmc_batch_workspace_bytes")
+        self.workspace = torch.empty(int(b.value), dtype=torch.uint8, device=self.sims[0].device)
+        self._handles = (ctypes.c_void_p * n)(*[s._h.value for s in self.sims])
+
+    def sweep(self, n_sweeps: int = 1, counters: bool = True):
+        n = len(self.sims)
+        out = (_Counters * n)() if counters else None
+        rc = lib().hpmc_sweep_batch(self._handles, n, ctypes.c_void_p(self.workspace.data_ptr()),
+                                    self.workspace.numel(), int(n_sweeps), out)
+        if rc != 0:
+            msg = lib().hpmc_last_error(self.sims[0]._h)
+            raise HpmcError(rc, f"sweep_batch: {msg.decode() if msg else ''}")
+        if not counters:
+            return None
+        return [{f: int(getattr(c, f)) for f in COUNTERS} for c in out]

@@ -54,6 +54,10 @@ struct hpmc_sim {
     int trace = 0;
     int trace_valid = 0;
     std::vector<hipEvent_t> events;  // timing of phase launches (counters requested)
+    Desc desc{};                     // host copy of the device descriptor
+    Desc* d_desc = nullptr;          // device descriptor (in the workspace)
+    unsigned long long* d_gather = nullptr;
+    int desc_dirty = 1;
     std::string err;
     ~hpmc_sim()
     {
@@ -121,7 +125,7 @@ int derive(hpmc_sim* s)
 
 struct Layout {
     size_t cell_count, cell_start, scan_tmp, pcell, prank, order, rpos, rquat, F, grid, perm, counters, flags, obs,
-        trace, total;
+        desc, sweep, gather, trace, total;
 };
 
 constexpr int kObsWords = 8192;
@@ -151,6 +155,9 @@ Layout layout(const hpmc_sim* s)
     l.counters = take(static_cast<size_t>(kCounterCopies) * kCounterStride * 8);
     l.flags = take(4 * 4);
     l.obs = take(static_cast<size_t>(kObsWords) * 8);
+    l.desc = take(sizeof(Desc));
+    l.sweep = take(4);
+    l.gather = take(kCounterStride * 8);
     l.trace = take(s->trace ? N * static_cast<size_t>(s->n_select) * sizeof(hpmc_move_record) : 0);
     l.total = off;
     return l;
@@ -176,6 +183,12 @@ void bind_work(hpmc_sim* s)
     W.flags = reinterpret_cast<int*>(b + l.flags);
     W.obs = reinterpret_cast<unsigned long long*>(b + l.obs);
     W.trace = s->trace ? static_cast<void*>(b + l.trace) : nullptr;
+    W.sweep_dev = reinterpret_cast<uint32_t*>(b + l.sweep);
+    W.pos = s->pos;
+    W.quat = s->quat;
+    s->d_desc = reinterpret_cast<Desc*>(b + l.desc);
+    s->d_gather = reinterpret_cast<unsigned long long*>(b + l.gather);
+    s->desc_dirty = 1;
 }
 
 int64_t packing_bound(const hpmc_sim* s, double side)
@@ -251,7 +264,60 @@ Params make_params(const hpmc_sim* s)
     return P;
 }
 
-StateRef state_ref(const hpmc_sim* s) { return StateRef{s->pos, s->quat}; }
+// launch shape of a group of replicas (descriptors already on the device)
+Group make_group(const Desc* d, const hpmc_sim* const* sims, int n)
+{
+    Group g{};
+    g.d = d;
+    g.nrep = n;
+    g.kind = sims[0]->S.kind;
+    g.wpb = 4;
+    size_t wave_lds = 0;
+    for (int i = 0; i < n; ++i) {
+        Params P = make_params(sims[i]);
+        g.maxN = std::max(g.maxN, P.N);
+        g.maxCells = std::max(g.maxCells, P.ncells);
+        g.maxActive = std::max(g.maxActive, P.active_cells);
+        g.wpb = std::min(g.wpb, P.waves_per_block);
+        wave_lds = std::max(wave_lds, static_cast<size_t>(P.wave_lds));
+    }
+    g.lds = kTableLds + static_cast<size_t>(g.wpb) * wave_lds;
+    return g;
+}
+
+Desc make_desc(const hpmc_sim* s, int wpb)
+{
+    Desc d{};
+    d.P = make_params(s);
+    d.P.waves_per_block = wpb;
+    d.W = s->W;
+    return d;
+}
+
+// refresh the device descriptor of a single handle when its host copy changed
+int sync_desc(hpmc_sim* s)
+{
+    Desc d = make_desc(s, make_params(s).waves_per_block);
+    if (!s->desc_dirty && memcmp(&d, &s->desc, sizeof(Desc)) == 0) return HPMC_OK;
+    s->desc = d;
+    hipError_t e = hipMemcpyAsync(s->d_desc, &s->desc, sizeof(Desc), hipMemcpyHostToDevice, s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "hipMemcpyAsync(descriptor)");
+    s->desc_dirty = 0;
+    return HPMC_OK;
+}
+
+Group single_group(hpmc_sim* s)
+{
+    const hpmc_sim* one[1] = {s};
+    return make_group(s->d_desc, one, 1);
+}
+
+int set_sweep_dev(hpmc_sim* s)
+{
+    hipError_t e = launch_fill_int(reinterpret_cast<int*>(s->W.sweep_dev), 1,
+                                   static_cast<int>(static_cast<uint32_t>(s->sweep)), s->stream);
+    return e == hipSuccess ? HPMC_OK : hip_fail(s, e, "sweep counter");
+}
 
 int check_ready(hpmc_sim* s, bool need_state)
 {
@@ -425,14 +491,22 @@ int hpmc_set_state(hpmc_sim* s, double* pos, double* quat, uint64_t sweep_index)
     if (r != HPMC_OK) return r;
     s->pos = pos;
     s->quat = s->S.oriented ? quat : nullptr;
+    s->W.pos = s->pos;
+    s->W.quat = s->quat;
     s->sweep = sweep_index;
     s->have_state = 1;
     s->trace_valid = 0;
+    r = sync_desc(s);
+    if (r == HPMC_OK) r = set_sweep_dev(s);
+    if (r != HPMC_OK) {
+        s->have_state = 0;
+        return r;
+    }
     // hard-core check on a cell list with zero shift
-    Params P = make_params(s);
-    hipError_t e = launch_build_cells(P, s->W, state_ref(s), false, s->stream);
+    Group g = single_group(s);
+    hipError_t e = launch_build_cells(g, false, s->stream);
     if (e == hipSuccess) e = launch_fill_u64(s->W.obs, 1, s->stream);
-    if (e == hipSuccess) e = launch_overlap_count(P, s->W, s->stream);
+    if (e == hipSuccess) e = launch_overlap_count(g, s->stream);
     unsigned long long cnt = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&cnt, s->W.obs, 8, hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -455,53 +529,56 @@ int hpmc_get_state(const hpmc_sim* s, uint64_t* sweep_index)
     return HPMC_OK;
 }
 
+namespace {
+
+// events: [0] call start, [1] call end, then (phases begin, phases end) per sweep
+int ensure_events(hpmc_sim* s, size_t need)
+{
+    while (s->events.size() < need) {
+        hipEvent_t ev;
+        hipError_t e = hipEventCreate(&ev);
+        if (e != hipSuccess) return hip_fail(s, e, "hipEventCreate");
+        s->events.push_back(ev);
+    }
+    return HPMC_OK;
+}
+
+void unpack_counters(const unsigned long long* host, hpmc_counters* out)
+{
+    memset(out, 0, sizeof(*out));
+    uint64_t* o = reinterpret_cast<uint64_t*>(out);
+    for (int k = 0; k < kNumCounters; ++k) o[k] = host[k];
+}
+
+}  // namespace
+
 int hpmc_sweep(hpmc_sim* s, int n_sweeps, hpmc_counters* out)
 {
     if (!s) return HPMC_EINVAL;
     if (n_sweeps < 0) return fail(s, HPMC_EINVAL, "negative sweep count");
     int r = check_ready(s, true);
-    if (r != HPMC_OK) return r;
-    r = upload_table(s);
-    if (r != HPMC_OK) return r;
-    hipError_t e = hipSuccess;
+    if (r == HPMC_OK) r = upload_table(s);
+    if (r == HPMC_OK) r = sync_desc(s);
     const bool timed = out != nullptr;
-    if (timed) {
-        size_t need = 2 * static_cast<size_t>(n_sweeps) + 2;
-        while (s->events.size() < need) {
-            hipEvent_t ev;
-            e = hipEventCreate(&ev);
-            if (e != hipSuccess) return hip_fail(s, e, "hipEventCreate");
-            s->events.push_back(ev);
-        }
-        e = hipEventRecord(s->events[0], s->stream);
-        if (e != hipSuccess) return hip_fail(s, e, "hipEventRecord");
-    }
-    e = launch_fill_u64(s->W.counters, kCounterCopies * kCounterStride, s->stream);
-    if (e == hipSuccess) e = launch_fill_int(s->W.flags, 4, 0, s->stream);
-    if (e != hipSuccess) return hip_fail(s, e, "sweep setup");
-    for (int i = 0; i < n_sweeps; ++i) {
-        Params P = make_params(s);
-        e = launch_build_cells(P, s->W, state_ref(s), true, s->stream);
-        if (e == hipSuccess && timed) e = hipEventRecord(s->events[2 + 2 * i], s->stream);
-        for (int p = 0; p < 8 && e == hipSuccess; ++p) e = launch_phase(P, s->W, p, s->stream);
-        if (e == hipSuccess && timed) e = hipEventRecord(s->events[3 + 2 * i], s->stream);
-        if (e == hipSuccess) e = launch_scatter_back(P, s->W, state_ref(s), s->stream);
-        if (e != hipSuccess) return hip_fail(s, e, "sweep launch");
+    if (r == HPMC_OK && timed) r = ensure_events(s, 2 * static_cast<size_t>(n_sweeps) + 2);
+    if (r != HPMC_OK) return r;
+    Group g = single_group(s);
+    hipError_t e = timed ? hipEventRecord(s->events[0], s->stream) : hipSuccess;
+    if (e == hipSuccess) e = launch_clear_counters(g, s->stream);
+    for (int i = 0; i < n_sweeps && e == hipSuccess; ++i) {
+        e = launch_sweep(g, timed ? s->events[2 + 2 * i] : nullptr, timed ? s->events[3 + 2 * i] : nullptr, s->stream);
         s->sweep++;
     }
+    if (e != hipSuccess) return hip_fail(s, e, "sweep launch");
     s->trace_valid = s->trace && n_sweeps > 0;
     if (out) {
         unsigned long long host[kCounterStride];
-        int flags = 0;
-        e = launch_reduce_counters(s->W, s->stream);
+        e = launch_reduce_counters(g, s->d_gather, s->stream);
         if (e == hipSuccess) e = hipEventRecord(s->events[1], s->stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(host, s->W.counters, sizeof(host), hipMemcpyDeviceToHost, s->stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(&flags, s->W.flags, 4, hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(host, s->d_gather, sizeof(host), hipMemcpyDeviceToHost, s->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
         if (e != hipSuccess) return hip_fail(s, e, "sweep counters");
-        memset(out, 0, sizeof(*out));
-        uint64_t* o = reinterpret_cast<uint64_t*>(out);
-        for (int k = 0; k < kNumCounters; ++k) o[k] = host[k];
+        unpack_counters(host, out);
         double phase_ms = 0.0;
         for (int i = 0; i < n_sweeps; ++i) {
             float ms = 0.0f;
@@ -514,7 +591,85 @@ int hpmc_sweep(hpmc_sim* s, int n_sweeps, hpmc_counters* out)
         if (e != hipSuccess) return hip_fail(s, e, "hipEventElapsedTime");
         out->phase_kernel_ms = phase_ms;
         out->sweep_ms = all;
-        if (flags) return fail(s, HPMC_ECAPACITY, "stencil or cell capacity exceeded (flags " + std::to_string(flags) + ")");
+        if (host[kNumCounters])
+            return fail(s, HPMC_ECAPACITY,
+                        "stencil or cell capacity exceeded (flags " + std::to_string(host[kNumCounters]) + ")");
+    }
+    return HPMC_OK;
+}
+
+int hpmc_batch_workspace_bytes(int n_sims, size_t* bytes)
+{
+    if (n_sims < 1 || !bytes) return HPMC_EINVAL;
+    *bytes = align256(static_cast<size_t>(n_sims) * sizeof(Desc)) +
+             align256(static_cast<size_t>(n_sims) * kCounterStride * 8);
+    return HPMC_OK;
+}
+
+int hpmc_sweep_batch(hpmc_sim* const* sims, int n_sims, void* batch_ws, size_t bytes, int n_sweeps,
+                     hpmc_counters* out)
+{
+    if (!sims || n_sims < 1 || n_sweeps < 0) return HPMC_EINVAL;
+    size_t need = 0;
+    hpmc_batch_workspace_bytes(n_sims, &need);
+    if (!batch_ws || bytes < need) {
+        if (sims[0]) fail(sims[0], HPMC_ENOMEM, "batch workspace missing or too small");
+        return HPMC_ENOMEM;
+    }
+    for (int i = 0; i < n_sims; ++i) {
+        if (!sims[i]) return HPMC_EINVAL;
+        int r = check_ready(sims[i], true);
+        if (r == HPMC_OK) r = upload_table(sims[i]);
+        if (r != HPMC_OK) return r;
+        if (sims[i]->trace) return fail(sims[i], HPMC_EINVAL, "tracing is per handle; disable it for batched sweeps");
+    }
+    hipStream_t st = sims[0]->stream;
+    // replicas that share a shape kind share each launch; groups run one after another
+    Desc* d_all = static_cast<Desc*>(batch_ws);
+    unsigned long long* d_gather = reinterpret_cast<unsigned long long*>(
+        static_cast<unsigned char*>(batch_ws) + align256(static_cast<size_t>(n_sims) * sizeof(Desc)));
+    std::vector<int> order;
+    for (int k = 0; k < 3; ++k)
+        for (int i = 0; i < n_sims; ++i)
+            if (sims[i]->S.kind == k) order.push_back(i);
+    std::vector<Desc> host(static_cast<size_t>(n_sims));
+    std::vector<Group> groups;
+    for (size_t b = 0; b < order.size();) {
+        size_t e = b;
+        while (e < order.size() && sims[order[e]]->S.kind == sims[order[b]]->S.kind) ++e;
+        std::vector<const hpmc_sim*> members;
+        for (size_t q = b; q < e; ++q) members.push_back(sims[order[q]]);
+        Group g = make_group(d_all + b, members.data(), static_cast<int>(members.size()));
+        for (size_t q = b; q < e; ++q) host[q] = make_desc(sims[order[q]], g.wpb);
+        groups.push_back(g);
+        b = e;
+    }
+    hipError_t e = hipMemcpyAsync(d_all, host.data(), host.size() * sizeof(Desc), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);  // the host copy is a local
+    for (const Group& g : groups)
+        if (e == hipSuccess) e = launch_clear_counters(g, st);
+    for (int sw = 0; sw < n_sweeps && e == hipSuccess; ++sw)
+        for (const Group& g : groups)
+            if (e == hipSuccess) e = launch_sweep(g, nullptr, nullptr, st);
+    if (e != hipSuccess) return hip_fail(sims[0], e, "batched sweep launch");
+    for (int i = 0; i < n_sims; ++i) sims[i]->sweep += static_cast<uint64_t>(n_sweeps);
+    if (out) {
+        std::vector<unsigned long long> hc(static_cast<size_t>(n_sims) * kCounterStride);
+        size_t off = 0;
+        for (const Group& g : groups) {
+            if (e == hipSuccess) e = launch_reduce_counters(g, d_gather + off * kCounterStride, st);
+            off += static_cast<size_t>(g.nrep);
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hc.data(), d_gather, hc.size() * 8, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(sims[0], e, "batched counters");
+        int flags = 0;
+        for (size_t q = 0; q < order.size(); ++q) {
+            unpack_counters(&hc[q * kCounterStride], &out[order[q]]);
+            flags |= static_cast<int>(hc[q * kCounterStride + kNumCounters]);
+        }
+        if (flags) return fail(sims[0], HPMC_ECAPACITY, "stencil or cell capacity exceeded in a batched sweep");
     }
     return HPMC_OK;
 }
@@ -542,9 +697,12 @@ int hpmc_observables(hpmc_sim* s, int kind, const hpmc_obs_params* p, double* ou
     if (!p || !out) return fail(s, HPMC_EINVAL, "null observable arguments");
     int r = check_ready(s, true);
     if (r != HPMC_OK) return r;
+    r = sync_desc(s);
+    if (r != HPMC_OK) return r;
     Params P = make_params(s);
+    Group g = single_group(s);
     const double V = s->L * s->L * s->L;
-    auto run_cells = [&]() { return launch_build_cells(P, s->W, state_ref(s), false, s->stream); };
+    auto run_cells = [&]() { return launch_build_cells(g, false, s->stream); };
     auto fetch = [&](int n, std::vector<unsigned long long>& h, int first) {
         h.assign(static_cast<size_t>(n), 0ull);
         hipError_t e = hipMemcpyAsync(h.data(), s->W.obs + first, static_cast<size_t>(n) * 8, hipMemcpyDeviceToHost,
@@ -558,7 +716,7 @@ int hpmc_observables(hpmc_sim* s, int kind, const hpmc_obs_params* p, double* ou
         if (nb < 1 || nb > kObsWords || out_len < nb || !(p->r_max > 0.0) || p->r_max > s->halfL)
             return fail(s, HPMC_EINVAL, "bad g(r) parameters");
         hipError_t e = run_cells();
-        if (e == hipSuccess) e = launch_gr(P, s->W, nb, p->r_max, s->stream);
+        if (e == hipSuccess) e = launch_gr(g, P, s->W, nb, p->r_max, s->stream);
         if (e == hipSuccess) e = fetch(nb, h, 0);
         if (e != hipSuccess) return hip_fail(s, e, "g(r)");
         double npair = 0.5 * static_cast<double>(s->N) * static_cast<double>(s->N - 1);
@@ -571,7 +729,7 @@ int hpmc_observables(hpmc_sim* s, int kind, const hpmc_obs_params* p, double* ou
         return HPMC_OK;
     }
     auto probes = [&](double scale, int slot) {
-        hipError_t e = launch_free_volume(P, s->W, p->n_probe, p->obs_seq, scale, slot, s->stream);
+        hipError_t e = launch_free_volume(g, p->n_probe, p->obs_seq, scale, slot, s->stream);
         return e;
     };
     if (kind == HPMC_OBS_FREE_VOLUME) {
@@ -595,7 +753,7 @@ int hpmc_observables(hpmc_sim* s, int kind, const hpmc_obs_params* p, double* ou
             p->n_fit > nb || p->n_probe < 0 || p->n_probe > 0xFFFFFFFFll)
             return fail(s, HPMC_EINVAL, "bad SDF parameters");
         hipError_t e = run_cells();
-        if (e == hipSuccess) e = launch_sdf(P, s->W, nb, p->x_max, s->stream);
+        if (e == hipSuccess) e = launch_sdf(g, P, s->W, nb, p->x_max, s->stream);
         if (e == hipSuccess) e = fetch(nb, h, 0);
         if (e != hipSuccess) return hip_fail(s, e, "SDF");
         double* hist = out + 4;

@@ -269,12 +269,21 @@ struct TrialOut {
 
 }  // namespace
 
+// Every kernel serves a group of independent replicas: blockIdx.y selects the
+// replica's descriptor (its constants and workspace); one handle is a group of one.
+#define HPMC_REPLICA(D)                     \
+    const Params P = (D)[blockIdx.y].P;     \
+    const Work W = (D)[blockIdx.y].W
+
 // ---------------------------------------------------------------------------
 // grid, cells
 // ---------------------------------------------------------------------------
-__global__ void grid_kernel(Params P, Work W, int with_grid)
+__global__ void grid_kernel(const Desc* __restrict__ D, int with_grid)
 {
+    Params P = D[blockIdx.y].P;
+    const Work W = D[blockIdx.y].W;
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    P.sweep = *W.sweep_dev;
     if (!with_grid) {
         for (int a = 0; a < 3; ++a) W.grid[a] = 0.0;
         for (int i = 0; i < 8; ++i) W.perm[i] = i;
@@ -297,6 +306,31 @@ __global__ void grid_kernel(Params P, Work W, int with_grid)
     for (int i = 0; i < 8; ++i) W.perm[i] = perm[i];
 }
 
+__global__ void clear_counters_kernel(const Desc* __restrict__ D)
+{
+    const Work W = D[blockIdx.y].W;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < kCounterCopies * kCounterStride) W.counters[i] = 0ull;
+    if (i < 4) W.flags[i] = 0;
+}
+
+__global__ void clear_cells_kernel(const Desc* __restrict__ D)
+{
+    HPMC_REPLICA(D);
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < P.ncells) W.cell_count[i] = 0;
+}
+
+// counters (13 per replica, after the reduction) and flags gathered for one copy
+__global__ void gather_counters_kernel(const Desc* __restrict__ D, int nrep, unsigned long long* out)
+{
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrep) return;
+    const Work W = D[r].W;
+    for (int k = 0; k < kNumCounters; ++k) out[static_cast<size_t>(r) * kCounterStride + k] = W.counters[k];
+    out[static_cast<size_t>(r) * kCounterStride + kNumCounters] = static_cast<unsigned long long>(W.flags[0]);
+}
+
 __global__ void fill_int_kernel(int* p, int n, int value)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -309,8 +343,10 @@ __global__ void fill_u64_kernel(unsigned long long* p, int n)
     if (i < n) p[i] = 0ull;
 }
 
-__global__ void bin_kernel(Params P, Work W, const double* __restrict__ pos)
+__global__ void bin_kernel(const Desc* __restrict__ D)
 {
+    HPMC_REPLICA(D);
+    const double* __restrict__ pos = W.pos;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P.N) return;
     int c = cell_of(P, pos[i], pos[P.N + i], pos[2 * P.N + i], W.grid[0], W.grid[1], W.grid[2]);
@@ -319,9 +355,14 @@ __global__ void bin_kernel(Params P, Work W, const double* __restrict__ pos)
 }
 
 // exclusive scan, 1024 elements per block of 256 threads
-__global__ __launch_bounds__(256) void scan_local_kernel(const int* __restrict__ in, int* __restrict__ out,
-                                                         int* __restrict__ totals, int n)
+__global__ __launch_bounds__(256) void scan_local_kernel(const Desc* __restrict__ D)
 {
+    HPMC_REPLICA(D);
+    const int* __restrict__ in = W.cell_count;
+    int* __restrict__ out = W.cell_start;
+    int* __restrict__ totals = W.scan_tmp;
+    const int n = P.ncells;
+    if (static_cast<int>(blockIdx.x) * 1024 >= n) return;
     __shared__ int wsum[4];
     int base = blockIdx.x * 1024 + threadIdx.x * 4;
     int v[4];
@@ -347,8 +388,12 @@ __global__ __launch_bounds__(256) void scan_local_kernel(const int* __restrict__
     if (threadIdx.x == 255) totals[blockIdx.x] = woff + ex + s;
 }
 
-__global__ __launch_bounds__(256) void scan_top_kernel(int* totals, int nblocks)
+__global__ __launch_bounds__(256) void scan_top_kernel(const Desc* __restrict__ D)
 {
+    HPMC_REPLICA(D);
+    int* totals = W.scan_tmp;
+    const int nblocks = (P.ncells + 1023) / 1024;
+    (void)P;
     __shared__ int wsum[4];
     __shared__ int carry;
     if (threadIdx.x == 0) carry = 0;
@@ -373,23 +418,29 @@ __global__ __launch_bounds__(256) void scan_top_kernel(int* totals, int nblocks)
     }
 }
 
-__global__ void scan_add_kernel(int* out, const int* totals, int n, int total_all)
+__global__ void scan_add_kernel(const Desc* __restrict__ D)
 {
+    HPMC_REPLICA(D);
+    int* out = W.cell_start;
+    const int* totals = W.scan_tmp;
+    const int n = P.ncells, total_all = P.N;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] += totals[i / 1024];
     if (i == 0) out[n] = total_all;
 }
 
-__global__ void scatter_kernel(Params P, Work W)
+__global__ void scatter_kernel(const Desc* __restrict__ D)
 {
+    HPMC_REPLICA(D);
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P.N) return;
     W.order[W.cell_start[W.pcell[i]] + W.prank[i]] = i;
 }
 
 // members of each cell in ascending particle index (insertion sort; cells are small)
-__global__ void sort_kernel(Params P, Work W)
+__global__ void sort_kernel(const Desc* __restrict__ D)
 {
+    HPMC_REPLICA(D);
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= P.ncells) return;
     int s = W.cell_start[c], e = W.cell_start[c + 1];
@@ -404,8 +455,11 @@ __global__ void sort_kernel(Params P, Work W)
     }
 }
 
-__global__ void gather_kernel(Params P, Work W, const double* __restrict__ pos, const double* __restrict__ quat)
+__global__ void gather_kernel(const Desc* __restrict__ D)
 {
+    HPMC_REPLICA(D);
+    const double* __restrict__ pos = W.pos;
+    const double* __restrict__ quat = W.quat;
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= P.N) return;
     int i = W.order[s];
@@ -414,9 +468,14 @@ __global__ void gather_kernel(Params P, Work W, const double* __restrict__ pos, 
         W.rquat[s] = make_double4(quat[i], quat[P.N + i], quat[2 * P.N + i], quat[3 * P.N + i]);
 }
 
-__global__ void scatter_back_kernel(Params P, Work W, double* __restrict__ pos, double* __restrict__ quat)
+// cell-ordered records back to the SoA state; the sweep counter advances here
+__global__ void scatter_back_kernel(const Desc* __restrict__ D, int advance)
 {
+    HPMC_REPLICA(D);
+    double* __restrict__ pos = W.pos;
+    double* __restrict__ quat = W.quat;
     int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (advance && s == 0) *W.sweep_dev = *W.sweep_dev + 1u;
     if (s >= P.N) return;
     double4 r = W.rpos[s];
     int i = static_cast<int>(r.w);
@@ -802,7 +861,6 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
 // the chunk runs its trials; neighbour ranges two cells ahead are loaded into
 // registers at the same time.  Trials then read only LDS and registers.
 // ---------------------------------------------------------------------------
-constexpr int kChunk = 16;
 constexpr int kStage = 64;  // staged stencil entries per cell (more are read from HBM)
 
 struct SphereStage {
@@ -1170,19 +1228,26 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
 #define HPMC_SPHERE_WAVES_PER_EU 3
 #endif
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HPMC_SPHERE_WAVES_PER_EU, 8))) void
-phase_sphere_kernel(Params P, Work W, int phase)
+phase_sphere_kernel(const Desc* __restrict__ D, int phase)
 {
+    Params P = D[blockIdx.y].P;
+    const Work W = D[blockIdx.y].W;
+    P.sweep = *W.sweep_dev;
     phase_sphere_body(P, W, phase);
 }
 
 template <int KIND>
-__global__ __launch_bounds__(256) void phase_oriented_kernel(Params P, Work W, int phase)
+__global__ __launch_bounds__(256) void phase_oriented_kernel(const Desc* __restrict__ D, int phase)
 {
+    Params P = D[blockIdx.y].P;
+    const Work W = D[blockIdx.y].W;
+    P.sweep = *W.sweep_dev;
     phase_body<KIND>(P, W, phase);
 }
 
-__global__ void reduce_counters_kernel(Work W)
+__global__ void reduce_counters_kernel(const Desc* __restrict__ D)
 {
+    const Work W = D[blockIdx.y].W;
     int k = threadIdx.x;
     if (k >= kNumCounters) return;
     unsigned long long s = 0;
@@ -1191,8 +1256,9 @@ __global__ void reduce_counters_kernel(Work W)
 }
 
 // hard-core check of a state: pairs (slot order) that overlap
-__global__ void overlap_count_kernel(Params P, Work W)
+__global__ void overlap_count_kernel(const Desc* __restrict__ D)
 {
+    HPMC_REPLICA(D);
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= P.N) return;
     double4 a = W.rpos[s];
@@ -1249,8 +1315,9 @@ __device__ inline int wrap_cell(int c, int n) { return ((c % n) + n) % n; }
 }  // namespace
 
 // pair-distance histogram (pairs i < j), W.obs[0..n_bins)
-__global__ __launch_bounds__(256) void gr_kernel(Params P, Work W, int n_bins, double r_max, int k)
+__global__ __launch_bounds__(256) void gr_kernel(const Desc* __restrict__ D, int n_bins, double r_max, int k)
 {
+    HPMC_REPLICA(D);
     extern __shared__ unsigned long long hist[];
     for (int b = threadIdx.x; b < n_bins; b += blockDim.x) hist[b] = 0ull;
     __syncthreads();
@@ -1290,9 +1357,10 @@ __global__ __launch_bounds__(256) void gr_kernel(Params P, Work W, int n_bins, d
 }
 
 // uniform probes that overlap no colloid (displacements scaled by `scale`)
-__global__ __launch_bounds__(256) void free_volume_kernel(Params P, Work W, int64_t n_probe, uint32_t seq,
+__global__ __launch_bounds__(256) void free_volume_kernel(const Desc* __restrict__ D, int64_t n_probe, uint32_t seq,
                                                           double scale, int slot)
 {
+    HPMC_REPLICA(D);
     int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     int free_ = 0;
     if (p < n_probe) {
@@ -1329,8 +1397,9 @@ __global__ __launch_bounds__(256) void free_volume_kernel(Params P, Work W, int6
 
 // per-particle smallest compression of a neighbour separation at which the
 // pair overlaps (scale-distribution function); histogram in W.obs
-__global__ __launch_bounds__(128) void sdf_kernel(Params P, Work W, int n_bins, double x_max, int k)
+__global__ __launch_bounds__(128) void sdf_kernel(const Desc* __restrict__ D, int n_bins, double x_max, int k)
 {
+    HPMC_REPLICA(D);
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= P.N) return;
     double4 a = W.rpos[s];
@@ -1416,60 +1485,70 @@ hipError_t launch_fill_u64(unsigned long long* p, int n, hipStream_t stream)
     return hipGetLastError();
 }
 
-hipError_t launch_build_cells(const Params& P, const Work& W, const StateRef& st, bool with_grid, hipStream_t stream)
+hipError_t launch_build_cells(const Group& g, bool with_grid, hipStream_t stream)
 {
-    hipLaunchKernelGGL(grid_kernel, dim3(1), dim3(64), 0, stream, P, W, with_grid ? 1 : 0);
-    hipError_t e = launch_fill_int(W.cell_count, P.ncells, 0, stream);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(bin_kernel, dim3(blocks_for(P.N, 256)), dim3(256), 0, stream, P, W,
-                       static_cast<const double*>(st.pos));
-    int nb = blocks_for(P.ncells, 1024);
-    hipLaunchKernelGGL(scan_local_kernel, dim3(nb), dim3(256), 0, stream, static_cast<const int*>(W.cell_count),
-                       W.cell_start, W.scan_tmp, P.ncells);
-    hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(256), 0, stream, W.scan_tmp, nb);
-    hipLaunchKernelGGL(scan_add_kernel, dim3(blocks_for(P.ncells, 256)), dim3(256), 0, stream, W.cell_start,
-                       static_cast<const int*>(W.scan_tmp), P.ncells, P.N);
-    hipLaunchKernelGGL(scatter_kernel, dim3(blocks_for(P.N, 256)), dim3(256), 0, stream, P, W);
-    hipLaunchKernelGGL(sort_kernel, dim3(blocks_for(P.ncells, 256)), dim3(256), 0, stream, P, W);
-    hipLaunchKernelGGL(gather_kernel, dim3(blocks_for(P.N, 256)), dim3(256), 0, stream, P, W,
-                       static_cast<const double*>(st.pos), static_cast<const double*>(st.quat));
+    const int R = g.nrep;
+    hipLaunchKernelGGL(grid_kernel, dim3(1, R), dim3(64), 0, stream, g.d, with_grid ? 1 : 0);
+    hipLaunchKernelGGL(clear_cells_kernel, dim3(blocks_for(g.maxCells, 256), R), dim3(256), 0, stream, g.d);
+    hipLaunchKernelGGL(bin_kernel, dim3(blocks_for(g.maxN, 256), R), dim3(256), 0, stream, g.d);
+    int nb = blocks_for(g.maxCells, 1024);
+    hipLaunchKernelGGL(scan_local_kernel, dim3(nb, R), dim3(256), 0, stream, g.d);
+    hipLaunchKernelGGL(scan_top_kernel, dim3(1, R), dim3(256), 0, stream, g.d);
+    hipLaunchKernelGGL(scan_add_kernel, dim3(blocks_for(g.maxCells, 256), R), dim3(256), 0, stream, g.d);
+    hipLaunchKernelGGL(scatter_kernel, dim3(blocks_for(g.maxN, 256), R), dim3(256), 0, stream, g.d);
+    hipLaunchKernelGGL(sort_kernel, dim3(blocks_for(g.maxCells, 256), R), dim3(256), 0, stream, g.d);
+    hipLaunchKernelGGL(gather_kernel, dim3(blocks_for(g.maxN, 256), R), dim3(256), 0, stream, g.d);
     return hipGetLastError();
 }
 
-hipError_t launch_phase(const Params& P, const Work& W, int phase, hipStream_t stream)
+hipError_t launch_phase(const Group& g, int phase, hipStream_t stream)
 {
-    size_t lds = kTableLds + static_cast<size_t>(P.waves_per_block) * P.wave_lds;
-    int waves = P.active_cells;
-    int max_waves = 256 * 32;
-    if (waves > max_waves) waves = max_waves;
-    if (P.S.kind == kSphere) waves = blocks_for(P.active_cells, kChunk);
-    int blocks = blocks_for(waves, P.waves_per_block);
-    dim3 bs(64 * P.waves_per_block);
-    switch (P.S.kind) {
-    case kSphere: hipLaunchKernelGGL(phase_sphere_kernel, dim3(blocks), bs, lds, stream, P, W, phase); break;
-    case kHemisphere:
-        hipLaunchKernelGGL(phase_oriented_kernel<kHemisphere>, dim3(blocks), bs, lds, stream, P, W, phase);
-        break;
-    default: hipLaunchKernelGGL(phase_oriented_kernel<kDiscoid>, dim3(blocks), bs, lds, stream, P, W, phase); break;
+    const int R = g.nrep;
+    dim3 bs(64 * g.wpb);
+    if (g.kind == kSphere) {
+        int waves = blocks_for(g.maxActive, kChunk);
+        hipLaunchKernelGGL(phase_sphere_kernel, dim3(blocks_for(waves, g.wpb), R), bs, g.lds, stream, g.d, phase);
+    } else {
+        int waves = g.maxActive < 256 * 32 ? g.maxActive : 256 * 32;
+        if (R > 1 && waves > 512) waves = 512;
+        dim3 grid(blocks_for(waves, g.wpb), R);
+        if (g.kind == kHemisphere)
+            hipLaunchKernelGGL(phase_oriented_kernel<kHemisphere>, grid, bs, g.lds, stream, g.d, phase);
+        else
+            hipLaunchKernelGGL(phase_oriented_kernel<kDiscoid>, grid, bs, g.lds, stream, g.d, phase);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_scatter_back(const Params& P, const Work& W, const StateRef& st, hipStream_t stream)
+hipError_t launch_sweep(const Group& g, hipEvent_t phases_begin, hipEvent_t phases_end, hipStream_t stream)
 {
-    hipLaunchKernelGGL(scatter_back_kernel, dim3(blocks_for(P.N, 256)), dim3(256), 0, stream, P, W, st.pos, st.quat);
+    hipError_t e = launch_build_cells(g, true, stream);
+    if (e == hipSuccess && phases_begin) e = hipEventRecord(phases_begin, stream);
+    for (int p = 0; p < 8 && e == hipSuccess; ++p) e = launch_phase(g, p, stream);
+    if (e == hipSuccess && phases_end) e = hipEventRecord(phases_end, stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(scatter_back_kernel, dim3(blocks_for(g.maxN, 256), g.nrep), dim3(256), 0, stream, g.d, 1);
     return hipGetLastError();
 }
 
-hipError_t launch_overlap_count(const Params& P, const Work& W, hipStream_t stream)
+hipError_t launch_clear_counters(const Group& g, hipStream_t stream)
 {
-    hipLaunchKernelGGL(overlap_count_kernel, dim3(blocks_for(P.N, 128)), dim3(128), 0, stream, P, W);
+    hipLaunchKernelGGL(clear_counters_kernel, dim3(blocks_for(kCounterCopies * kCounterStride, 256), g.nrep),
+                       dim3(256), 0, stream, g.d);
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_counters(const Work& W, hipStream_t stream)
+hipError_t launch_overlap_count(const Group& g, hipStream_t stream)
 {
-    hipLaunchKernelGGL(reduce_counters_kernel, dim3(1), dim3(64), 0, stream, W);
+    hipLaunchKernelGGL(overlap_count_kernel, dim3(blocks_for(g.maxN, 128), g.nrep), dim3(128), 0, stream, g.d);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_counters(const Group& g, unsigned long long* gather_out, hipStream_t stream)
+{
+    hipLaunchKernelGGL(reduce_counters_kernel, dim3(1, g.nrep), dim3(64), 0, stream, g.d);
+    hipLaunchKernelGGL(gather_counters_kernel, dim3(blocks_for(g.nrep, 64)), dim3(64), 0, stream, g.d, g.nrep,
+                       gather_out);
     return hipGetLastError();
 }
 
@@ -1477,32 +1556,32 @@ hipError_t launch_reduce_counters(const Work& W, hipStream_t stream)
 
 namespace hpmc {
 
-hipError_t launch_gr(const Params& P, const Work& W, int n_bins, double r_max, hipStream_t stream)
+hipError_t launch_gr(const Group& g, const Params& P, const Work& W, int n_bins, double r_max, hipStream_t stream)
 {
     hipError_t e = launch_fill_u64(W.obs, n_bins, stream);
     if (e != hipSuccess) return e;
     int k = static_cast<int>(ceil(r_max * P.inv_w));
-    hipLaunchKernelGGL(gr_kernel, dim3(blocks_for(P.N, 256)), dim3(256), n_bins * sizeof(unsigned long long), stream,
-                       P, W, n_bins, r_max, k);
+    hipLaunchKernelGGL(gr_kernel, dim3(blocks_for(P.N, 256), 1), dim3(256), n_bins * sizeof(unsigned long long), stream,
+                       g.d, n_bins, r_max, k);
     return hipGetLastError();
 }
 
-hipError_t launch_free_volume(const Params& P, const Work& W, int64_t n_probe, uint32_t seq, double scale, int slot,
+hipError_t launch_free_volume(const Group& g, int64_t n_probe, uint32_t seq, double scale, int slot,
                               hipStream_t stream)
 {
     int64_t blocks = (n_probe + 255) / 256;
-    hipLaunchKernelGGL(free_volume_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, P, W, n_probe,
+    hipLaunchKernelGGL(free_volume_kernel, dim3(static_cast<unsigned>(blocks), 1), dim3(256), 0, stream, g.d, n_probe,
                        seq, scale, slot);
     return hipGetLastError();
 }
 
-hipError_t launch_sdf(const Params& P, const Work& W, int n_bins, double x_max, hipStream_t stream)
+hipError_t launch_sdf(const Group& g, const Params& P, const Work& W, int n_bins, double x_max, hipStream_t stream)
 {
     hipError_t e = launch_fill_u64(W.obs, n_bins, stream);
     if (e != hipSuccess) return e;
     double lim_s = 2.0 * P.S.rcirc / (1.0 - x_max);
     int k = static_cast<int>(ceil(lim_s * P.inv_w));
-    hipLaunchKernelGGL(sdf_kernel, dim3(blocks_for(P.N, 128)), dim3(128), 0, stream, P, W, n_bins, x_max, k);
+    hipLaunchKernelGGL(sdf_kernel, dim3(blocks_for(P.N, 128), 1), dim3(128), 0, stream, g.d, n_bins, x_max, k);
     return hipGetLastError();
 }
 

@@ -77,24 +77,41 @@ struct Work {
     void* trace;       // hpmc_move_record[N * n_select] or null
     int* flags;
     unsigned long long* obs;  // observables scratch
+    uint32_t* sweep_dev;      // sweep index of the random streams, advanced on the device
+    double* pos;              // caller's state [3][N]
+    double* quat;             // caller's orientations [4][N] or null
 };
 
-struct StateRef {
-    double* pos;   // [3][N]
-    double* quat;  // [4][N] or null
+// per-replica descriptor in device memory
+struct Desc {
+    Params P;
+    Work W;
+};
+
+// host-side launch shape of a group of replicas of one shape kind
+struct Group {
+    const Desc* d;  // device array of nrep descriptors
+    int nrep;
+    int kind;
+    int maxN, maxCells, maxActive;
+    int wpb;        // waves per block of the phase kernel (common to the group)
+    size_t lds;     // dynamic LDS bytes of the phase kernel (common to the group)
 };
 
 // host-side launchers (enqueue on `stream`)
 hipError_t launch_fill_int(int* p, int n, int value, hipStream_t stream);
 hipError_t launch_fill_u64(unsigned long long* p, int n, hipStream_t stream);
-hipError_t launch_build_cells(const Params& P, const Work& W, const StateRef& st, bool with_grid, hipStream_t stream);
-hipError_t launch_phase(const Params& P, const Work& W, int phase, hipStream_t stream);
-hipError_t launch_scatter_back(const Params& P, const Work& W, const StateRef& st, hipStream_t stream);
-hipError_t launch_overlap_count(const Params& P, const Work& W, hipStream_t stream);
-hipError_t launch_reduce_counters(const Work& W, hipStream_t stream);
-hipError_t launch_gr(const Params& P, const Work& W, int n_bins, double r_max, hipStream_t stream);
-hipError_t launch_free_volume(const Params& P, const Work& W, int64_t n_probe, uint32_t seq, double scale,
-                              int slot, hipStream_t stream);
-hipError_t launch_sdf(const Params& P, const Work& W, int n_bins, double x_max, hipStream_t stream);
+hipError_t launch_build_cells(const Group& g, bool with_grid, hipStream_t stream);
+hipError_t launch_phase(const Group& g, int phase, hipStream_t stream);
+hipError_t launch_sweep(const Group& g, hipEvent_t phases_begin, hipEvent_t phases_end, hipStream_t stream);
+hipError_t launch_clear_counters(const Group& g, hipStream_t stream);
+hipError_t launch_overlap_count(const Group& g, hipStream_t stream);
+hipError_t launch_reduce_counters(const Group& g, unsigned long long* gather_out, hipStream_t stream);
+hipError_t launch_gr(const Group& g, const Params& P, const Work& W, int n_bins, double r_max, hipStream_t stream);
+hipError_t launch_free_volume(const Group& g, int64_t n_probe, uint32_t seq, double scale, int slot,
+                              hipStream_t stream);
+hipError_t launch_sdf(const Group& g, const Params& P, const Work& W, int n_bins, double x_max, hipStream_t stream);
+
+constexpr int kChunk = 16;  // active cells per wave of the sphere phase kernel
 
 }  // namespace hpmc
