@@ -82,6 +82,7 @@ enum {
     P_CB_FWD = 7,
     P_CB_REV = 8,
     P_ACCEPT = 9,
+    P_DEPL_SHELL = 10,
     P_OBS_FV = 16
 };
 #define NO_CELL 0xFFFFFFFFu
@@ -133,6 +134,27 @@ int orc_ball_candidate(uint32_t wa, uint32_t wb, int32_t m[3])
         s += mi * mi;
     }
     return s < ((int64_t)1 << 42);
+}
+
+/* Uniform point in the spherical shell r_i <= |e| < R0 (Sec. III.C: any
+ * region V_0 that holds every depletant that can block the move may be used;
+ * the inner ball lies inside the old pose for every allowed move, so a
+ * depletant there is never free in M).  One candidate per Philox block:
+ * direction by Marsaglia's method (1972) from two symmetric uniforms, radius
+ * uniform in [r_i, R0) accepted with probability r^2 / R0^2, so the density
+ * is proportional to r^2 on the shell.  IEEE + - * sqrt only, in this order. */
+int orc_shell_candidate(const uint32_t w[4], double r_i, double span, double R0sq, double e[3])
+{
+    double x1 = sym01(w[0]), x2 = sym01(w[1]);
+    double s = x1 * x1 + x2 * x2;
+    if (!(s < 1.0)) return 0;
+    double r = r_i + span * u01(w[2]);
+    if (!(u01(w[3]) * R0sq < r * r)) return 0;
+    double h = 2.0 * sqrt(1.0 - s);
+    e[0] = r * (x1 * h);
+    e[1] = r * (x2 * h);
+    e[2] = r * (1.0 - 2.0 * s);
+    return 1;
 }
 
 /* k-th accepted candidate of a ball stream; candidates are taken in the order
@@ -215,6 +237,7 @@ typedef struct {
     double a;     /* hemisphere radius d/2; discoid disk radius */
     double rs;    /* discoid sweep radius */
     double rcirc; /* circumradius about the reference point */
+    double rin;   /* radius of the largest ball about the reference point inside the shape */
     double vol;
     int oriented;
 } shape_t;
@@ -228,6 +251,7 @@ static int shape_setup(shape_t* sh, int kind, const double* p, int np)
         sh->d = p[0];
         sh->a = 0.5 * p[0];
         sh->rcirc = 0.5 * p[0];
+        sh->rin = 0.5 * p[0];
         sh->vol = M_PI * p[0] * p[0] * p[0] / 6.0;
         sh->oriented = 0;
     } else if (kind == ORC_HEMISPHERE) {
@@ -235,6 +259,7 @@ static int shape_setup(shape_t* sh, int kind, const double* p, int np)
         sh->d = p[0];
         sh->a = 0.5 * p[0];
         sh->rcirc = 0.5 * p[0];
+        sh->rin = 0.0; /* the face centre lies on the boundary */
         sh->vol = M_PI * p[0] * p[0] * p[0] / 12.0;
         sh->oriented = 1;
     } else if (kind == ORC_DISCOID) {
@@ -243,6 +268,7 @@ static int shape_setup(shape_t* sh, int kind, const double* p, int np)
         sh->rs = p[1];
         sh->d = 2.0 * (p[0] + p[1]);
         sh->rcirc = p[0] + p[1];
+        sh->rin = p[1];
         sh->vol = 2.0 * M_PI * p[0] * p[0] * p[1] + M_PI * M_PI * p[0] * p[1] * p[1] +
                   4.0 / 3.0 * M_PI * p[1] * p[1] * p[1];
         sh->oriented = 1;
@@ -576,6 +602,8 @@ struct orc_sim {
     /* derived */
     int n;
     double w, inv_w, R0, R0sq, lambda, lambda_c, s_ball;
+    int region;            /* ORC_V0_BALL or ORC_V0_SHELL */
+    double r_inner, span;  /* shell: inner radius and R0 - r_inner */
     int n_chunks;
     double F[POISSON_K];
     /* state */
@@ -652,6 +680,16 @@ static int derive(orc_sim* s)
     s->inv_w = 1.0 / s->w;
     s->s_ball = s->R0 * 0x1p-21;
     double vol0 = 4.0 / 3.0 * M_PI * s->R0 * s->R0 * s->R0;
+    s->r_inner = 0.0;
+    s->span = s->R0;
+    if (s->region == ORC_V0_SHELL) {
+        /* a translation moves the centre by at most sqrt(3) d_trans */
+        double ri = (s->sh.rin + s->r_dep) - sqrt(3.0) * s->d_trans;
+        if (ri < 0.0) ri = 0.0;
+        s->r_inner = ri;
+        s->span = s->R0 - ri;
+        vol0 = 4.0 / 3.0 * M_PI * (s->R0 * s->R0 * s->R0 - ri * ri * ri);
+    }
     s->lambda = s->z_p * vol0;
     int m = (int)ceil(s->lambda / POISSON_CHUNK);
     if (m < 1) m = 1;
@@ -696,7 +734,14 @@ int orc_set_moves(orc_sim* s, double d_trans, double a_rot, double p_rot, int n_
     s->a_rot = a_rot;
     s->p_rot = (s->have_shape && !s->sh.oriented) ? 0.0 : p_rot;
     s->n_select = n_select;
-    return 0;
+    return derive(s);
+}
+
+int orc_set_insertion(orc_sim* s, int region)
+{
+    if (region != ORC_V0_BALL && region != ORC_V0_SHELL) return fail(s, -1, "invalid insertion region");
+    s->region = region;
+    return derive(s);
 }
 
 int orc_set_state(orc_sim* s, const double* pos, const double* quat, uint64_t sweep_index)
@@ -728,9 +773,10 @@ int orc_set_trace(orc_sim* s, int enable)
 
 int orc_derived(const orc_sim* s, double* out, int out_len)
 {
-    double v[12] = {(double)s->n, s->w, s->inv_w, s->R0, s->lambda, (double)s->n_chunks, s->lambda_c,
-                    s->s_ball, s->r_dep, s->sh.rcirc, s->sh.vol, s->halfL};
-    for (int i = 0; i < out_len && i < 12; ++i) out[i] = v[i];
+    double v[14] = {(double)s->n, s->w,         s->inv_w,    s->R0,     s->lambda,
+                    (double)s->n_chunks, s->lambda_c, s->s_ball, s->r_dep, s->sh.rcirc,
+                    s->sh.vol,   s->halfL,     s->r_inner,  s->span};
+    for (int i = 0; i < out_len && i < 14; ++i) out[i] = v[i];
     return 0;
 }
 
@@ -852,13 +898,26 @@ static int trial(orc_sim* s, int64_t j, const double xn[3], const double qn[4], 
 
         ball_stream_t bs;
         ball_stream_init(&bs, st, P_DEPL, 0);
+        uint32_t shell_block = 0;
         uint64_t resolved = 0, cbt = 0;
         uint32_t nblk = 0, wf = 0, wr = 0;
         double ratio = 1.0;
         for (uint32_t k = 0; k < Np && reason == ORC_ACCEPT; ++k) {
-            int32_t m[3];
-            ball_stream_next(&bs, m, 0xFFFFFFFFu);
-            double e[3] = {s->s_ball * (double)m[0], s->s_ball * (double)m[1], s->s_ball * (double)m[2]};
+            double e[3];
+            if (s->region == ORC_V0_SHELL) {
+                /* k-th accepted block of the shell stream */
+                for (;;) {
+                    uint32_t w[4];
+                    draw(st, P_DEPL_SHELL, shell_block++, w);
+                    if (orc_shell_candidate(w, s->r_inner, s->span, s->R0sq, e)) break;
+                }
+            } else {
+                int32_t m[3];
+                ball_stream_next(&bs, m, 0xFFFFFFFFu);
+                e[0] = s->s_ball * (double)m[0];
+                e[1] = s->s_ball * (double)m[1];
+                e[2] = s->s_ball * (double)m[2];
+            }
             resolved++;
             /* irrelevant: does not overlap the moved colloid in M' (always overlaps for spheres) */
             if (sh->kind != ORC_SPHERE && !dep_overlap(sh, s->r_dep, e, Rnew)) continue;

@@ -13,7 +13,8 @@
  *   - target distribution exp(z_p V_f - beta H_cc)            Sec. III.A, Eq. (gc_ensemble)
  *   - trial move + Poisson depletants + reject if a depletant
  *     that was free in M overlaps M'                           Sec. III.B, Eqs. (move_gen), (pacc)
- *   - sampling region V_0 = circumsphere of the new pose       Sec. III.C, Eq. (transition_prob_final)
+ *   - sampling region V_0 = circumsphere of the new pose, or
+ *     that ball less a core inside the old pose (shell)       Sec. III.C, Eq. (transition_prob_final)
  *   - configurational-bias re-insertion                        Sec. III.D, Eq. (pacc_cb), Fig. 3
  *   - checkerboard cells, random colour order, random shift   Sec. III.E
  */
@@ -42,6 +43,12 @@ enum {
 };
 
 enum { ORC_OBS_GR = 0, ORC_OBS_FREE_VOLUME = 1, ORC_OBS_SDF = 2 };
+
+/* depletant insertion region V_0 (Sec. III.C) */
+enum {
+    ORC_V0_BALL = 0,  /* circumsphere B(x', R0) of the new pose */
+    ORC_V0_SHELL = 1  /* B(x', R0) minus B(x', r_in + r_dep - sqrt(3) d_trans) */
+};
 
 /* One record per trial, laid out exactly like the GPU library's record. */
 typedef struct orc_record {
@@ -96,6 +103,7 @@ const char* orc_last_error(const orc_sim* s);
 int orc_set_shape(orc_sim* s, int kind, const double* params, int nparams);
 int orc_set_fugacity(orc_sim* s, double z_p, double d_dep, int n_trial);
 int orc_set_moves(orc_sim* s, double d_trans, double a_rot, double p_rot, int n_select);
+int orc_set_insertion(orc_sim* s, int region);
 int orc_set_state(orc_sim* s, const double* pos_soa, const double* quat_soa, uint64_t sweep_index);
 int orc_get_state(const orc_sim* s, double* pos_soa, double* quat_soa, uint64_t* sweep_index);
 int orc_set_trace(orc_sim* s, int enable);
@@ -120,6 +128,7 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 int orc_poisson_table(double lambda_c, double* F, int K);
 int orc_poisson_draw(const double* F, int K, double u);
 int orc_ball_candidate(uint32_t wa, uint32_t wb, int32_t m[3]);
+int orc_shell_candidate(const uint32_t w[4], double r_i, double span, double R0sq, double e[3]);
 int orc_depletant_overlap(int kind, const double* params, double r_dep,
                           const double* v_world, const double* quat);
 int orc_pair_overlap(int kind, const double* params, const double* d_world,

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 SPHERE, HEMISPHERE, DISCOID = 0, 1, 2
 ACCEPT, REJ_CELL_EXIT, REJ_OVERLAP, REJ_DEPLETANT, REJ_CB_ZERO, REJ_CB_METROPOLIS = range(6)
 OBS_GR, OBS_FREE_VOLUME, OBS_SDF = 0, 1, 2
+V0_BALL, V0_SHELL = 0, 1
 
 RECORD_DTYPE = np.dtype(
     [
@@ -125,6 +126,9 @@ def lib():
         L.orc_poisson_table.argtypes = [ctypes.c_double, c_d_p, ctypes.c_int]
         L.orc_poisson_draw.argtypes = [c_d_p, ctypes.c_int, ctypes.c_double]
         L.orc_ball_candidate.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int32)]
+        L.orc_shell_candidate.argtypes = [ctypes.POINTER(ctypes.c_uint32), ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_double, c_d_p]
+        L.orc_set_insertion.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.orc_depletant_overlap.argtypes = [ctypes.c_int, c_d_p, ctypes.c_double, c_d_p, c_d_p]
         L.orc_pair_overlap.argtypes = [ctypes.c_int, c_d_p, c_d_p, c_d_p, c_d_p, ctypes.POINTER(ctypes.c_int)]
         _lib = L
@@ -158,6 +162,13 @@ def ball_candidate(wa: int, wb: int):
     m = (ctypes.c_int32 * 3)()
     ok = lib().orc_ball_candidate(wa & 0xFFFFFFFF, wb & 0xFFFFFFFF, m)
     return bool(ok), (m[0], m[1], m[2])
+
+
+def shell_candidate(words, r_i: float, span: float, R0sq: float):
+    w = (ctypes.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in words])
+    e = (ctypes.c_double * 3)()
+    ok = lib().orc_shell_candidate(w, float(r_i), float(span), float(R0sq), e)
+    return bool(ok), (e[0], e[1], e[2])
 
 
 def depletant_overlap(kind: int, params, r_dep: float, v_world, quat=None) -> bool:
@@ -209,6 +220,9 @@ class OracleSim:
     def set_moves(self, d_trans: float, a_rot: float = 0.0, p_rot: float = 0.0, n_select: int = 1):
         self._chk(lib().orc_set_moves(self._h, float(d_trans), float(a_rot), float(p_rot), int(n_select)))
 
+    def set_insertion(self, region: int):
+        self._chk(lib().orc_set_insertion(self._h, int(region)))
+
     def set_state(self, pos: np.ndarray, quat: np.ndarray | None = None, sweep: int = 0):
         pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(3, self.n)
         qp = None
@@ -246,9 +260,10 @@ class OracleSim:
         return buf[: nw.value].copy()
 
     def derived(self) -> dict:
-        out = np.zeros(12, dtype=np.float64)
-        lib().orc_derived(self._h, _dp(out), 12)
-        keys = ["n", "w", "inv_w", "R0", "lambda", "n_chunks", "lambda_c", "s_ball", "r_dep", "rcirc", "vol", "halfL"]
+        out = np.zeros(14, dtype=np.float64)
+        lib().orc_derived(self._h, _dp(out), 14)
+        keys = ["n", "w", "inv_w", "R0", "lambda", "n_chunks", "lambda_c", "s_ball", "r_dep", "rcirc", "vol", "halfL",
+                "r_inner", "span"]
         return dict(zip(keys, out.tolist()))
 
     def count_overlaps(self) -> int:
