@@ -59,6 +59,10 @@ extern "C" {
 #define HPMC_FP64 0          /* all geometry in FP64 */
 #define HPMC_FP32_GUARDED 1  /* FP32 depletant geometry, FP64 recomputation inside a guard band */
 
+/* depletant insertion region V_0 (hpmc_set_insertion) */
+#define HPMC_V0_BALL 0   /* the circumsphere B(x', R0) of the new pose, R0 = R_circ + d_dep/2 */
+#define HPMC_V0_SHELL 1  /* B(x', R0) less the core B(x', r_in + d_dep/2 - sqrt(3) d_trans) */
+
 /* trial outcomes (hpmc_move_record.reason) */
 #define HPMC_ACCEPT 0
 #define HPMC_REJ_CELL_EXIT 1
@@ -151,6 +155,18 @@ int hpmc_set_fugacity(hpmc_sim* sim, double z_p, double d_dep, int n_trial);
  * rotation q' = (q + a_rot v)/|q + a_rot v| with v uniform in the unit 4-ball.
  * n_select trials per cell member and sweep.  Errors: EINVAL. */
 int hpmc_set_moves(hpmc_sim* sim, double d_trans, double a_rot, double p_rot, int n_select);
+
+/* Depletant insertion region (Sec. III.C: V_0 may be any region that holds
+ * every depletant able to block the move).  HPMC_V0_BALL (default): the
+ * circumsphere of the new pose.  HPMC_V0_SHELL: that ball less a core ball of
+ * radius r_in + d_dep/2 - sqrt(3) d_trans (clamped at 0), r_in being the
+ * largest ball about the reference point inside the shape (sphere d/2,
+ * hemisphere 0, swept disk r_s); a depletant in the core overlaps the old pose
+ * for every translation of at most sqrt(3) d_trans and so is never free.  The
+ * shell mode draws its depletants from its own random stream (one candidate
+ * per Philox block), so its trajectories differ from the ball mode's while
+ * sampling the same ensemble.  Errors: EINVAL (unknown region). */
+int hpmc_set_insertion(hpmc_sim* sim, int region);
 
 /* Bytes of device workspace this handle needs with the current shape,
  * fugacity, moves and trace setting. */

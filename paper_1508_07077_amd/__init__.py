@@ -19,6 +19,7 @@ SPHERE, HEMISPHERE, DISCOID = 0, 1, 2
 FP64, FP32_GUARDED = 0, 1
 ACCEPT, REJ_CELL_EXIT, REJ_OVERLAP, REJ_DEPLETANT, REJ_CB_ZERO, REJ_CB_METROPOLIS = range(6)
 OBS_GR, OBS_FREE_VOLUME, OBS_SDF = 0, 1, 2
+V0_BALL, V0_SHELL = 0, 1
 
 ERRORS = {
     -1: "HPMC_EINVAL",
@@ -37,6 +38,7 @@ EXPORTS = (
     "hpmc_set_shape",
     "hpmc_set_fugacity",
     "hpmc_set_moves",
+    "hpmc_set_insertion",
     "hpmc_workspace_bytes",
     "hpmc_set_workspace",
     "hpmc_set_state",
@@ -116,6 +118,7 @@ def lib():
         L.hpmc_set_shape.argtypes = [vp, cint, dp, cint]
         L.hpmc_set_fugacity.argtypes = [vp, dbl, dbl, cint]
         L.hpmc_set_moves.argtypes = [vp, dbl, dbl, dbl, cint]
+        L.hpmc_set_insertion.argtypes = [vp, cint]
         L.hpmc_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
         L.hpmc_set_workspace.argtypes = [vp, vp, ctypes.c_size_t]
         L.hpmc_set_state.argtypes = [vp, vp, vp, u64]
@@ -185,6 +188,11 @@ class Sim:
     def set_moves(self, d_trans: float, a_rot: float = 0.0, p_rot: float = 0.0, n_select: int = 1):
         self._chk(lib().hpmc_set_moves(self._h, float(d_trans), float(a_rot), float(p_rot), int(n_select)),
                   "set_moves")
+
+    def set_insertion(self, region: int):
+        """V0_BALL (circumsphere of the new pose) or V0_SHELL (that ball less the core
+        that stays inside the old pose)."""
+        self._chk(lib().hpmc_set_insertion(self._h, int(region)), "set_insertion")
 
     def set_trace(self, enable: bool = True):
         self._chk(lib().hpmc_set_trace(self._h, 1 if enable else 0), "set_trace")

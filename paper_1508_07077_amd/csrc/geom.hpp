@@ -75,6 +75,7 @@ struct Shape {
     double a;        // hemisphere radius d/2; discoid disk radius
     double rs;       // discoid sweep radius
     double rcirc;    // circumradius about the reference point
+    double rin;      // radius of the largest ball about the reference point inside the shape
     double dsq;      // sphere: d^2
     double r_dep;    // depletant radius
     double R0sq;     // (rcirc + r_dep)^2 : sphere and hemisphere dome threshold

@@ -36,9 +36,11 @@ struct hpmc_sim {
     int n_trial = 0;
     double d_trans = 0.1, a_rot = 0, p_rot = 0;
     int n_select = 1;
+    int region = HPMC_V0_BALL;
     // derived
     int n = 0;
     double w = 0, inv_w = 0, R0 = 0, lambda = 0, lambda_c = 0, s_ball = 0;
+    double r_inner = 0, span = 0;  // shell region: inner radius, R0 - r_inner
     int n_chunks = 1;
     double F[kPoissonK];
     int G[kGuide];  // guide: first k with F[k] >= i / kGuide
@@ -54,6 +56,8 @@ struct hpmc_sim {
     int trace = 0;
     int trace_valid = 0;
     std::vector<hipEvent_t> events;  // timing of phase launches (counters requested)
+    hipGraphExec_t graph = nullptr;  // one captured sweep, replayed for untimed multi-sweep calls
+    std::vector<unsigned char> graph_key;
     Desc desc{};                     // host copy of the device descriptor
     Desc* d_desc = nullptr;          // device descriptor (in the workspace)
     unsigned long long* d_gather = nullptr;
@@ -62,6 +66,7 @@ struct hpmc_sim {
     ~hpmc_sim()
     {
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        if (graph) (void)hipGraphExecDestroy(graph);
     }
 };
 
@@ -97,6 +102,16 @@ int derive(hpmc_sim* s)
     s->inv_w = 1.0 / s->w;
     s->s_ball = s->R0 * 0x1p-21;
     double vol0 = 4.0 / 3.0 * M_PI * s->R0 * s->R0 * s->R0;
+    s->r_inner = 0.0;
+    s->span = s->R0;
+    if (s->region == HPMC_V0_SHELL) {
+        // the core ball stays inside the old pose for translations up to sqrt(3) d_trans
+        double ri = (s->S.rin + r_dep) - sqrt(3.0) * s->d_trans;
+        if (ri < 0.0) ri = 0.0;
+        s->r_inner = ri;
+        s->span = s->R0 - ri;
+        vol0 = 4.0 / 3.0 * M_PI * (s->R0 * s->R0 * s->R0 - ri * ri * ri);
+    }
     s->lambda = s->z_p * vol0;
     int m = static_cast<int>(ceil(s->lambda / 256.0));
     if (m < 1) m = 1;
@@ -225,6 +240,9 @@ Params make_params(const hpmc_sim* s)
     P.a_rot = s->a_rot;
     P.p_rot = s->S.oriented ? s->p_rot : 0.0;
     P.s_ball = s->s_ball;
+    P.shell = s->region == HPMC_V0_SHELL;
+    P.r_inner = s->r_inner;
+    P.span = s->span;
     // per-wave LDS of the phase kernel: rigorous packing bounds (hard bodies
     // are disjoint) for the stencil list and own-cell records
     double rc2 = 2.0 * s->S.rcirc;
@@ -380,6 +398,7 @@ int hpmc_set_shape(hpmc_sim* s, int kind, const double* p, int np)
         if (np < 1 || !(p[0] > 0.0) || !isfinite(p[0])) return fail(s, HPMC_EINVAL, "diameter must be positive");
         S.a = 0.5 * p[0];
         S.rcirc = 0.5 * p[0];
+        S.rin = (kind == HPMC_SPHERE) ? 0.5 * p[0] : 0.0;  // hemisphere: the face centre is on the boundary
         S.dsq = p[0] * p[0];
         S.oriented = kind == HPMC_HEMISPHERE;
         vol = (kind == HPMC_SPHERE) ? M_PI * p[0] * p[0] * p[0] / 6.0 : M_PI * p[0] * p[0] * p[0] / 12.0;
@@ -388,6 +407,7 @@ int hpmc_set_shape(hpmc_sim* s, int kind, const double* p, int np)
         S.a = p[0];
         S.rs = p[1];
         S.rcirc = p[0] + p[1];
+        S.rin = p[1];
         S.dsq = 4.0 * S.rcirc * S.rcirc;
         S.oriented = 1;
         vol = 2.0 * M_PI * p[0] * p[0] * p[1] + M_PI * M_PI * p[0] * p[1] * p[1] + 4.0 / 3.0 * M_PI * p[1] * p[1] * p[1];
@@ -443,10 +463,33 @@ int hpmc_set_moves(hpmc_sim* s, double d_trans, double a_rot, double p_rot, int 
     if (!(d_trans >= 0.0) || !isfinite(d_trans) || !(a_rot >= 0.0) || !isfinite(a_rot) || !(p_rot >= 0.0 && p_rot <= 1.0) ||
         n_select < 1 || n_select > 1024)
         return fail(s, HPMC_EINVAL, "invalid move parameters");
+    double od = s->d_trans;
     s->d_trans = d_trans;
+    int r = derive(s);  // the shell region depends on d_trans
+    if (r != HPMC_OK) {
+        s->d_trans = od;
+        derive(s);
+        return r;
+    }
     s->a_rot = a_rot;
     s->p_rot = p_rot;
     s->n_select = n_select;
+    if (s->ws) bind_work(s);
+    return HPMC_OK;
+}
+
+int hpmc_set_insertion(hpmc_sim* s, int region)
+{
+    if (!s) return HPMC_EINVAL;
+    if (region != HPMC_V0_BALL && region != HPMC_V0_SHELL) return fail(s, HPMC_EINVAL, "unknown insertion region");
+    int o = s->region;
+    s->region = region;
+    int r = derive(s);
+    if (r != HPMC_OK) {
+        s->region = o;
+        derive(s);
+        return r;
+    }
     if (s->ws) bind_work(s);
     return HPMC_OK;
 }
@@ -469,6 +512,8 @@ int hpmc_set_workspace(hpmc_sim* s, void* dev_ptr, size_t bytes)
     s->ws_bytes = bytes;
     s->F_dirty = 1;
     bind_work(s);
+    // the device-side sweep counter lives in the workspace: carry it over
+    if (s->have_state) return set_sweep_dev(s);
     return HPMC_OK;
 }
 
@@ -531,6 +576,43 @@ int hpmc_get_state(const hpmc_sim* s, uint64_t* sweep_index)
 
 namespace {
 
+// Untimed sweeps of a fixed launch shape replay one captured sweep (a hipGraph
+// of its ~20 kernels): the kernels read descriptors and the sweep counter from
+// device memory, so the graph stays valid while the groups' shapes do.
+hipError_t run_sweeps(hpmc_sim* owner, const std::vector<Group>& groups, int n, hipStream_t st)
+{
+    std::vector<unsigned char> key(groups.size() * sizeof(Group));
+    if (!groups.empty()) memcpy(key.data(), groups.data(), key.size());
+    hipError_t e = hipSuccess;
+    if (n >= 2 && st != nullptr) {
+        if (!owner->graph || owner->graph_key != key) {
+            if (owner->graph) {
+                (void)hipGraphExecDestroy(owner->graph);
+                owner->graph = nullptr;
+            }
+            hipGraph_t graph = nullptr;
+            e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+            for (const Group& g : groups)
+                if (e == hipSuccess) e = launch_sweep(g, nullptr, nullptr, st);
+            hipError_t e2 = hipStreamEndCapture(st, &graph);
+            if (e == hipSuccess) e = e2;
+            if (e == hipSuccess) e = hipGraphInstantiate(&owner->graph, graph, nullptr, nullptr, 0);
+            if (graph) (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                owner->graph = nullptr;
+                return e;
+            }
+            owner->graph_key = key;
+        }
+        for (int i = 0; i < n && e == hipSuccess; ++i) e = hipGraphLaunch(owner->graph, st);
+        return e;
+    }
+    for (int i = 0; i < n && e == hipSuccess; ++i)
+        for (const Group& g : groups)
+            if (e == hipSuccess) e = launch_sweep(g, nullptr, nullptr, st);
+    return e;
+}
+
 // events: [0] call start, [1] call end, then (phases begin, phases end) per sweep
 int ensure_events(hpmc_sim* s, size_t need)
 {
@@ -565,11 +647,14 @@ int hpmc_sweep(hpmc_sim* s, int n_sweeps, hpmc_counters* out)
     Group g = single_group(s);
     hipError_t e = timed ? hipEventRecord(s->events[0], s->stream) : hipSuccess;
     if (e == hipSuccess) e = launch_clear_counters(g, s->stream);
-    for (int i = 0; i < n_sweeps && e == hipSuccess; ++i) {
-        e = launch_sweep(g, timed ? s->events[2 + 2 * i] : nullptr, timed ? s->events[3 + 2 * i] : nullptr, s->stream);
-        s->sweep++;
+    if (timed) {
+        for (int i = 0; i < n_sweeps && e == hipSuccess; ++i)
+            e = launch_sweep(g, s->events[2 + 2 * i], s->events[3 + 2 * i], s->stream);
+    } else if (e == hipSuccess) {
+        e = run_sweeps(s, std::vector<Group>{g}, n_sweeps, s->stream);
     }
     if (e != hipSuccess) return hip_fail(s, e, "sweep launch");
+    s->sweep += static_cast<uint64_t>(n_sweeps);
     s->trace_valid = s->trace && n_sweeps > 0;
     if (out) {
         unsigned long long host[kCounterStride];
@@ -648,9 +733,7 @@ int hpmc_sweep_batch(hpmc_sim* const* sims, int n_sims, void* batch_ws, size_t b
     if (e == hipSuccess) e = hipStreamSynchronize(st);  // the host copy is a local
     for (const Group& g : groups)
         if (e == hipSuccess) e = launch_clear_counters(g, st);
-    for (int sw = 0; sw < n_sweeps && e == hipSuccess; ++sw)
-        for (const Group& g : groups)
-            if (e == hipSuccess) e = launch_sweep(g, nullptr, nullptr, st);
+    if (e == hipSuccess) e = run_sweeps(sims[0], groups, n_sweeps, st);
     if (e != hipSuccess) return hip_fail(sims[0], e, "batched sweep launch");
     for (int i = 0; i < n_sims; ++i) sims[i]->sweep += static_cast<uint64_t>(n_sweeps);
     if (out) {

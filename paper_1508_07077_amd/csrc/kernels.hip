@@ -107,6 +107,28 @@ __device__ inline Words draw(const Params& P, uint32_t cell, uint32_t t, uint32_
 }
 
 // 4-ball candidate: 25-bit fields, odd m in (-2^25, 2^25), accepted iff sum m^2 < 2^50
+// depletant candidates of block `blk` of a trial's insertion stream: two ball
+// candidates (V_0 = B(x', R0)) or one shell candidate (V_0 = the shell)
+__device__ inline void depl_candidates(const Params& P, uint32_t cell, uint32_t t, uint32_t blk, bool& acc0, bool& acc1,
+                                       Vec3& e0, Vec3& e1)
+{
+    if (P.shell) {
+        Words dw = draw(P, cell, t, kDeplShell, blk);
+        double x, y, z;
+        acc0 = shell3(dw, P.r_inner, P.span, P.S.R0sq, x, y, z);
+        acc1 = false;
+        e0 = v3(x, y, z);
+        e1 = e0;
+    } else {
+        Words dw = draw(P, cell, t, kDepl, blk);
+        double a0, a1, a2, b0, b1, b2;
+        acc0 = ball3(dw.w0, dw.w1, a0, a1, a2);
+        acc1 = ball3(dw.w2, dw.w3, b0, b1, b2);
+        e0 = v3(P.s_ball * a0, P.s_ball * a1, P.s_ball * a2);
+        e1 = v3(P.s_ball * b0, P.s_ball * b1, P.s_ball * b2);
+    }
+}
+
 __device__ inline bool ball4(Words w, double m[4])
 {
     uint32_t ws[4] = {w.w0, w.w1, w.w2, w.w3};
@@ -698,7 +720,7 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
                 if (__ballot(hit) != 0ull) {
                     o.reason = 2;
                 } else if (P.has_dep) {
-                    // --- Poisson number of depletants in V_0 = B(x', R0) ----------
+                    // --- Poisson number of depletants in V_0 ------------------------
                     int kc = 0;
                     if (lane >= 3 && lane < 32 && lane - 3 < P.n_chunks) kc = poisson_guided(sF, sG, u52(w.w0, w.w1));
                     for (int base = 29; base < P.n_chunks; base += 64) {
@@ -718,16 +740,14 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
                     bool done = false;
                     uint32_t kbase = 0, blk = 0;
                     while (!done && kbase < Np && blk < (1u << 30)) {
-                        Words dw = draw(P, static_cast<uint32_t>(C), static_cast<uint32_t>(t), kDepl, blk + lane);
-                        double a0, a1, a2, b0, b1, b2;
-                        bool acc0 = ball3(dw.w0, dw.w1, a0, a1, a2);
-                        bool acc1 = ball3(dw.w2, dw.w3, b0, b1, b2);
+                        bool acc0, acc1;
+                        Vec3 e0, e1;
+                        depl_candidates(P, static_cast<uint32_t>(C), static_cast<uint32_t>(t), blk + lane, acc0, acc1,
+                                        e0, e1);
                         unsigned long long m0 = __ballot(acc0), m1 = __ballot(acc1);
                         uint32_t k0 = kbase + static_cast<uint32_t>(bits_below(m0) + bits_below(m1));
                         uint32_t k1 = k0 + (acc0 ? 1u : 0u);
                         bool v0 = acc0 && k0 < Np, v1 = acc1 && k1 < Np;
-                        Vec3 e0 = v3(P.s_ball * a0, P.s_ball * a1, P.s_ball * a2);
-                        Vec3 e1 = v3(P.s_ball * b0, P.s_ball * b1, P.s_ball * b2);
                         // irrelevant (misses M') or ignored by the old pose
                         if (v0) {
                             if constexpr (ORI) v0 = dep_ov<KIND>(P.S, e0, Rn);
@@ -1075,15 +1095,13 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
                         bool done = false;
                         uint32_t kbase = 0, blk = 0;
                         while (!done && kbase < Np && blk < (1u << 30)) {
-                            Words dw = draw(P, static_cast<uint32_t>(C), static_cast<uint32_t>(t), kDepl, blk + lane);
-                            double a0, a1, a2, b0, b1, b2;
-                            bool acc0 = ball3(dw.w0, dw.w1, a0, a1, a2);
-                            bool acc1 = ball3(dw.w2, dw.w3, b0, b1, b2);
+                            bool acc0, acc1;
+                            Vec3 e0, e1;
+                            depl_candidates(P, static_cast<uint32_t>(C), static_cast<uint32_t>(t), blk + lane, acc0,
+                                            acc1, e0, e1);
                             unsigned long long m0 = __ballot(acc0), m1 = __ballot(acc1);
                             uint32_t k0 = kbase + static_cast<uint32_t>(bits_below(m0) + bits_below(m1));
                             uint32_t k1 = k0 + (acc0 ? 1u : 0u);
-                            Vec3 e0 = v3(P.s_ball * a0, P.s_ball * a1, P.s_ball * a2);
-                            Vec3 e1 = v3(P.s_ball * b0, P.s_ball * b1, P.s_ball * b2);
                             // ignored by the old pose (every ball point overlaps the new pose)
                             bool v0 = acc0 && k0 < Np && !(dot(e0 - Dold, e0 - Dold) < P.S.R0sq);
                             bool v1 = acc1 && k1 < Np && !(dot(e1 - Dold, e1 - Dold) < P.S.R0sq);

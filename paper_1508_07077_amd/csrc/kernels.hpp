@@ -52,6 +52,8 @@ struct Params {
     double L, halfL, w, inv_w;
     double d_trans, a_rot, p_rot;
     double s_ball;  // R0 * 2^-21
+    int shell;      // depletants in the shell r_inner <= |e| < R0 instead of the ball
+    double r_inner, span;  // span = R0 - r_inner
     // per-wave LDS layout of the phase kernel
     int list_cap, own_cap, geo_cap;
     int wave_lds;       // bytes per wave

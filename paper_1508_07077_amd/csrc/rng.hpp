@@ -23,6 +23,7 @@ enum Purpose : uint32_t {
     kCbFwd = 7,
     kCbRev = 8,
     kAccept = 9,
+    kDeplShell = 10,
     kObsFv = 16,
 };
 
@@ -96,6 +97,24 @@ __host__ __device__ inline bool ball3(uint32_t wa, uint32_t wb, double& m0, doub
     // every partial sum is an integer below 2^44: the fused form is exact
     double s = fma(m0, m0, fma(m1, m1, m2 * m2));
     return s < 0x1p42;
+}
+
+// Point uniform in the shell r_i <= |e| < R0 from one block: direction by
+// Marsaglia's method (two symmetric uniforms inside the unit disk), radius
+// uniform in [r_i, R0) kept with probability r^2 / R0^2.  Plain IEEE
+// + - * sqrt in a fixed order (compiled without contraction).
+__host__ __device__ inline bool shell3(const Words& w, double r_i, double span, double R0sq, double& e0, double& e1,
+                                       double& e2)
+{
+    double x1 = sym01(w.w0), x2 = sym01(w.w1);
+    double s = x1 * x1 + x2 * x2;
+    double r = r_i + span * u01(w.w2);
+    bool ok = (s < 1.0) && (u01(w.w3) * R0sq < r * r);
+    double h = 2.0 * sqrt(ok ? 1.0 - s : 1.0);
+    e0 = r * (x1 * h);
+    e1 = r * (x2 * h);
+    e2 = r * (1.0 - 2.0 * s);
+    return ok;
 }
 
 }  // namespace hpmc

@@ -7,7 +7,7 @@ TRACE_FIELDS = ("sweep", "cell", "t", "particle", "n_depletants", "resolved", "n
                 "phase", "reason", "rotation")
 
 
-def make_pair(sp, pos, quat=None, sweep=0, trace=True, precision=0):
+def make_pair(sp, pos, quat=None, sweep=0, trace=True, precision=0, region=0):
     import paper_1508_07077_amd as hp
     from oracle import pyoracle
 
@@ -17,6 +17,7 @@ def make_pair(sp, pos, quat=None, sweep=0, trace=True, precision=0):
         s.set_shape(sp.kind, sp.params)
         s.set_fugacity(sp.z_p, sp.d_dep, sp.n_trial)
         s.set_moves(sp.d_trans, sp.a_rot, sp.p_rot)
+        s.set_insertion(region)
         s.set_trace(trace)
     g.set_state(pos, quat, sweep)
     o.set_state(pos, quat, sweep)
