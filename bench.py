@@ -40,6 +40,14 @@ VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 #   per depletant = 0.955 * (60 + 2 * 15) + 14 = 100.0 lane-instructions
 ALGO_OPS_PER_CHECK = 0.955 * (60 + 2 * 15) + 14
 
+# Shell insertion region: one candidate per block (60), 4 u32->f64 conversions
+# with their offsets and scalings (12), the disk test (3), the radius and its
+# r^2 test (5), 2 sqrt(1 - s) + direction + 3 scalings (16): 96 per block,
+# accepted with probability (pi/4) E[r^2]/R0^2; + 14 per accepted depletant.
+def shell_ops_per_check(R0: float, r_i: float) -> float:
+    acc = math.pi / 4 * (R0**3 - r_i**3) / (3.0 * (R0 - r_i) * R0**2)
+    return 96.0 / acc + 14.0
+
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -50,6 +58,13 @@ def parse():
     ap.add_argument("--n", type=int, default=1048576)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle CPU-baseline budget (0 disables)")
     ap.add_argument("--cpu-n", type=int, default=40000)
+    ap.add_argument("--workload", default="c3", choices=["c3", "c1", "c2", "c4", "c5"],
+                    help="c3: 1,048,576 spheres (default); c1: 64 spheres, 1000 sweeps; "
+                         "c2: 16384 hemispheres, eta_r 0.1..0.4; c4: 256 batched discoid replicas; "
+                         "c5: Poisson request stream served with continuous batching")
+    ap.add_argument("--v0", default="ball", choices=["ball", "shell"],
+                    help="c3: depletant insertion region of the headline run (the other one is timed after it)")
+    ap.add_argument("--serve-seconds", type=float, default=10.0, help="c5: length of the arrival trace")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (scales the HBM byte counters)")
     return ap.parse_args()
@@ -117,6 +132,9 @@ def main():
     from paper_1508_07077_amd import workloads as wl
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload != "c3":
+        print(json.dumps(OTHER[args.workload](args)), flush=True)
+        return
     sp = wl.c3_spheres_large(n=args.n)
     pos, _ = sp.initial_state()
     sim = hp.Sim(sp.n, sp.L, sp.seed)
@@ -128,27 +146,33 @@ def main():
         sim.sweep(args.melt, counters=False)
     sim.set_fugacity(sp.z_p, sp.d_dep, sp.n_trial)
     sim.set_moves(sp.d_trans)
+    region = hp.V0_SHELL if args.v0 == "shell" else hp.V0_BALL
+    sim.set_insertion(region)
     sim.ensure_workspace()
-    for _ in range(args.warmup):
-        sim.sweep(1, counters=True)
-    torch.cuda.synchronize()
-    tot = None
-    lat = []
-    phase_ms = 0.0
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        c = sim.sweep(1, counters=True)
-        lat.append((time.perf_counter() - ts) * 1e3)
-        phase_ms += c["phase_kernel_ms"]
-        tot = c if tot is None else {k: tot[k] + c[k] for k in tot}
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    tot, lat, phase_ms, dt = _timed_sweeps(torch, sim, args.steps, args.warmup)
     moves = tot["trials"] / dt
     checks = tot["depletants_resolved"] / dt
     launches = 8 * args.steps
     avg_phase_s = phase_ms / 1e3 / launches
-    achieved = ALGO_OPS_PER_CHECK * (tot["depletants_resolved"] / launches) / avg_phase_s
+    R0 = 0.5 * sp.params[0] + 0.5 * sp.d_dep
+    ops_per_check = ALGO_OPS_PER_CHECK if region == hp.V0_BALL else \
+        shell_ops_per_check(R0, max(0.0, R0 - math.sqrt(3.0) * sp.d_trans))
+    achieved = ops_per_check * (tot["depletants_resolved"] / launches) / avg_phase_s
+    # the same state point with the other insertion region, timed right after
+    other = hp.V0_BALL if region == hp.V0_SHELL else hp.V0_SHELL
+    sim.set_insertion(other)
+    sim.ensure_workspace()
+    tot2, lat2, _, dt2 = _timed_sweeps(torch, sim, args.steps, args.warmup)
+    companion = {
+        "insertion_region": "shell" if other == hp.V0_SHELL else "ball",
+        "moves_per_s": tot2["trials"] / dt2,
+        "depletant_checks_per_s": tot2["depletants_resolved"] / dt2,
+        "ms_per_step": dt2 * 1e3 / args.steps,
+        "p50_ms": float(np.percentile(lat2, 50)),
+        "p99_ms": float(np.percentile(lat2, 99)),
+        "acceptance": tot2["accepts"] / tot2["trials"],
+        "depletants_per_move": tot2["depletants_drawn"] / tot2["trials"],
+    }
     line = {
         "metric": "colloid trial moves/s + depletant overlap checks/s (1 GPU); p50/p99 latency",
         "value": moves,
@@ -165,8 +189,10 @@ def main():
         "config": {
             "workload": f"hard spheres N={sp.n} phi_c={sp.phi_c} cubic periodic box L={sp.L:.4f}; "
                         f"sphere depletants q={sp.q} eta_r={sp.eta_r} (z_p={sp.z_p:.3f}); n_trial={sp.n_trial}; "
-                        f"translation delta={sp.d_trans}; one step = one sweep of N trial moves",
+                        f"translation delta={sp.d_trans}; one step = one sweep of N trial moves; "
+                        f"depletants inserted in the {args.v0} region",
             "N": sp.n,
+            "insertion_region": args.v0,
             "sweeps_timed": args.steps,
         },
         "depletant_checks_per_s": checks,
@@ -184,13 +210,221 @@ def main():
             "frac": achieved / VALU_PEAK_LANE_OPS,
             "traffic": None,
             "avg_launch_ms": avg_phase_s * 1e3,
-            "ops_per_check": ALGO_OPS_PER_CHECK,
+            "ops_per_check": ops_per_check,
         },
+        "other_insertion_region": companion,
     }
     if args.cpu_seconds > 0:
         line["cpu_baseline"] = cpu_baseline(lambda n: wl.c3_spheres_large(n=n, d_trans=sp.d_trans), args.cpu_n,
                                             args.cpu_seconds)
     print(json.dumps(line), flush=True)
+
+
+def _timed_sweeps(torch, sim, steps, warmup):
+    """warmup untimed sweeps, then `steps` timed sweeps of one step each:
+    (summed counters, per-step latencies in ms, summed phase-kernel ms, seconds)"""
+    for _ in range(warmup):
+        sim.sweep(1, counters=True)
+    torch.cuda.synchronize()
+    tot = None
+    lat = []
+    phase_ms = 0.0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        c = sim.sweep(1, counters=True)
+        lat.append((time.perf_counter() - ts) * 1e3)
+        phase_ms += c["phase_kernel_ms"]
+        tot = c if tot is None else {k: tot[k] + c[k] for k in tot}
+    torch.cuda.synchronize()
+    return tot, lat, phase_ms, time.perf_counter() - t0
+
+
+def _make(hp, sp, melt=20):
+    pos, quat = sp.initial_state()
+    sim = hp.Sim(sp.n, sp.L, sp.seed, sp.replica_id)
+    sim.set_shape(sp.kind, sp.params)
+    sim.set_fugacity(0.0, sp.d_dep, 0)
+    sim.set_moves(0.1, 0.1 if sp.kind != 0 else 0.0, sp.p_rot)
+    sim.set_state(pos, quat)
+    if melt:
+        sim.sweep(melt, counters=False)
+    sim.set_fugacity(sp.z_p, sp.d_dep, sp.n_trial)
+    sim.set_moves(sp.d_trans, sp.a_rot, sp.p_rot)
+    sim.ensure_workspace()
+    return sim
+
+
+def _line(metric_value, tot, dt, steps, warmup, workload, extra):
+    d = {
+        "metric": "colloid trial moves/s + depletant overlap checks/s (1 GPU); p50/p99 latency",
+        "value": metric_value,
+        "unit": "colloid trial moves/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": dt * 1e3 / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": workload},
+        "depletant_checks_per_s": tot["depletants_resolved"] / dt,
+        "acceptance": tot["accepts"] / max(tot["trials"], 1),
+    }
+    d.update(extra)
+    return d
+
+
+def bench_c1(args):
+    """64 spheres, 1000 sweeps: launch/latency bound.  Throughput from one
+    untimed 1000-sweep call (a replayed captured sweep); latency per sweep from
+    timed single-sweep calls."""
+    import numpy as np
+    import torch
+
+    import paper_1508_07077_amd as hp
+    from paper_1508_07077_amd import workloads as wl
+
+    sp = wl.c1_spheres_small()
+    sim = _make(hp, sp, melt=100)
+    sim.sweep(10, counters=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.sweep(1000, counters=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    lat = []
+    tot = None
+    for _ in range(200):
+        ts = time.perf_counter()
+        c = sim.sweep(1, counters=True)
+        lat.append((time.perf_counter() - ts) * 1e3)
+        tot = c if tot is None else {k: tot[k] + c[k] for k in tot}
+    return _line(1000 * sp.n / dt, {"depletants_resolved": tot["depletants_resolved"] * 1000 / 200,
+                                     "accepts": tot["accepts"], "trials": tot["trials"]}, dt, 1000, 10,
+                 "hard spheres N=64 phi_c=0.10 q=0.25 eta_r=0.10 delta=0.1, 1000 sweeps (graph replay)",
+                 {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                  "latency_note": "per-sweep latency of timed single-sweep calls (launch + counter readback)"})
+
+
+def bench_c2(args):
+    """16384 hemispheres at phi_c = 0.20, q = 0.15, eta_r = 0.1 .. 0.4,
+    translate + rotate (p_rot = 0.5), FP64."""
+    import numpy as np
+    import torch
+
+    import paper_1508_07077_amd as hp
+    from paper_1508_07077_amd import workloads as wl
+
+    per = {}
+    moves = checks = secs = 0.0
+    lat = []
+    for eta in (0.1, 0.2, 0.3, 0.4):
+        sp = wl.c2_hemispheres(eta)
+        sim = _make(hp, sp)
+        for _ in range(3):
+            sim.sweep(1, counters=True)
+        torch.cuda.synchronize()
+        tot = None
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ts = time.perf_counter()
+            c = sim.sweep(1, counters=True)
+            lat.append((time.perf_counter() - ts) * 1e3)
+            tot = c if tot is None else {k: tot[k] + c[k] for k in tot}
+        dt = time.perf_counter() - t0
+        per[str(eta)] = {"moves_per_s": tot["trials"] / dt, "depletant_checks_per_s": tot["depletants_resolved"] / dt,
+                         "acceptance": tot["accepts"] / tot["trials"], "ms_per_sweep": dt * 1e3 / args.steps,
+                         "z_p": sp.z_p, "delta": sp.d_trans, "near_contact_trials": tot["near_contact"]}
+        moves += tot["trials"]
+        checks += tot["depletants_resolved"]
+        secs += dt
+    d = _line(moves / secs, {"depletants_resolved": checks, "accepts": 1, "trials": 1}, secs, 4 * args.steps,
+              3, "hemispheres N=16384 phi_c=0.20 q=0.15 eta_r in {0.1,0.2,0.3,0.4}, p_rot=0.5, FP64",
+              {"per_eta_r": per, "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))})
+    d.pop("acceptance")
+    return d
+
+
+def bench_c4(args):
+    """256 independent discoid replicas (disk 0.5 swept by 0.1), N log-uniform in
+    [128, 8192], phi_c U[0.05, 0.45], eta_r U[0, 0.5], q = 0.2, swept together."""
+    import numpy as np
+    import torch
+
+    import paper_1508_07077_amd as hp
+    from paper_1508_07077_amd import workloads as wl
+
+    sps = wl.c4_discoid_replicas()
+    sims = [_make(hp, sp) for sp in sps]
+    b = hp.Batch(sims)
+    for _ in range(3):
+        b.sweep(1, counters=True)
+    torch.cuda.synchronize()
+    lat = []
+    tot = None
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        cs = b.sweep(1, counters=True)
+        lat.append((time.perf_counter() - ts) * 1e3)
+        c = {k: sum(x[k] for x in cs) for k in cs[0]}
+        tot = c if tot is None else {k: tot[k] + c[k] for k in tot}
+    dt = time.perf_counter() - t0
+    return _line(tot["trials"] / dt, tot, dt, args.steps, 3,
+                 f"256 swept-disk replicas, N={sum(s.n for s in sps)} in total (128..8192 each), "
+                 "phi_c U[0.05,0.45], eta_r U[0,0.5], q=0.2, one launch per kernel for all replicas",
+                 {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                  "replicas": len(sps)})
+
+
+def bench_c5(args):
+    """Poisson arrivals at 50 req/s of {sphere, hemisphere, discoid} requests,
+    N log-uniform in [256, 65536], phi_c in [0.05, 0.45], eta_r in [0, 0.5],
+    100 sweeps each, returning g(r), the free-volume fraction and the SDF
+    pressure; HBM-budget admission and continuous batching (serve.Server)."""
+    import torch
+
+    from paper_1508_07077_amd import serve
+    from paper_1508_07077_amd import workloads as wl
+
+    specs = wl.c5_request_stream(duration_s=args.serve_seconds)
+    reqs = [serve.Request(sp, sp.extra["sweeps"], sp.extra["arrival_s"], rid=i) for i, sp in enumerate(specs)]
+    srv = serve.Server(sweeps_per_tick=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = srv.run(reqs, realtime=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    summ = serve.latency_summary(done)
+    errors = sum(1 for r in done if "error" in r.result)
+    return {
+        "metric": "colloid trial moves/s + depletant overlap checks/s (1 GPU); p50/p99 latency",
+        "value": srv.moves / dt,
+        "unit": "colloid trial moves/s",
+        "n_gpus": 1,
+        "steps": len(done),
+        "warmup": 0,
+        "ms_per_step": dt * 1e3 / max(len(done), 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"request stream: Poisson arrivals 50 req/s for {args.serve_seconds} s, "
+                               "{sphere q=0.10, hemisphere q=0.15, discoid q=0.2}, N log-uniform [256, 65536], "
+                               "phi_c U[0.05,0.45], eta_r U[0,0.5], 100 sweeps + g(r), alpha, SDF each"},
+        "p50_ms": summ["p50_s"] * 1e3,
+        "p99_ms": summ["p99_s"] * 1e3,
+        "requests": summ["requests"],
+        "failed_requests": errors,
+        "latency_note": "per request, arrival to observables returned",
+    }
+
+
+OTHER = {"c1": bench_c1, "c2": bench_c2, "c4": bench_c4, "c5": bench_c5}
 
 
 if __name__ == "__main__":

@@ -64,11 +64,49 @@ def random_quaternions(n: int, rng: np.random.Generator) -> np.ndarray:
     return q
 
 
+def cubic_sites(m: int, L: float, d_min: float) -> np.ndarray:
+    """m points of the periodic box [0, L)^3, pairwise (minimum-image) farther
+    apart than d_min: the simple-cubic, body-centred or face-centred cubic
+    lattice (k^3, 2k^3 or 4k^3 sites) with the largest nearest-neighbour
+    distance that holds at least m sites, thinned evenly to m.  ValueError
+    when none of the three is loose enough.  Returns [3][m]."""
+    best = None
+    for per, nn_frac, basis in ((1, 1.0, [(0.0, 0.0, 0.0)]),
+                               (2, math.sqrt(3.0) / 2.0, [(0.0, 0.0, 0.0), (0.5, 0.5, 0.5)]),
+                               (4, 1.0 / math.sqrt(2.0), [(0.0, 0.0, 0.0), (0.5, 0.5, 0.0),
+                                                          (0.5, 0.0, 0.5), (0.0, 0.5, 0.5)])):
+        k = max(1, int(math.ceil((m / per) ** (1.0 / 3.0) - 1e-9)))
+        while per * k**3 < m:
+            k += 1
+        nn = nn_frac * L / k
+        if best is None or nn > best[0]:
+            best = (nn, k, basis)
+    nn, k, basis = best
+    if nn <= d_min * (1.0 + 1e-6):
+        raise ValueError("density too high for an overlap-free cubic lattice")
+    a = L / k
+    cells = np.arange(k**3)
+    ix, iy, iz = cells % k, (cells // k) % k, cells // (k * k)
+    pts = np.concatenate([np.stack([(ix + 0.25 + bx) * a, (iy + 0.25 + by) * a, (iz + 0.25 + bz) * a])
+                          for bx, by, bz in basis], axis=1)
+    keep = (np.arange(m, dtype=np.int64) * pts.shape[1]) // m
+    return np.ascontiguousarray(pts[:, keep].astype(np.float64))
+
+
+def _flip_quaternions(q: np.ndarray) -> np.ndarray:
+    """q * (0, 1, 0, 0): the same orientation turned by pi about the body x
+    axis, so that the body z axis points the opposite way."""
+    w, x, y, z = q
+    return np.stack([-x, w, z, -y])
+
+
 def lattice_state(n: int, L: float, kind: int, params, seed: int):
-    """Overlap-free starting state: simple-cubic sites (first n of k^3) when the
-    spacing exceeds the circumdiameter (any orientation is then safe);
-    otherwise, for discoids, aligned disks in columns.  Returns (pos[3][n],
-    quat[4][n] or None)."""
+    """Overlap-free starting state.  Simple-cubic sites (first n of k^3) when
+    the spacing exceeds the circumdiameter (any orientation is then safe);
+    otherwise spheres on the loosest of sc/bcc/fcc that fits, hemispheres in
+    flat-face-to-face pairs (each pair inside a ball of diameter 1.002 d) on
+    such a lattice, and discoids as aligned disks in columns.  Returns
+    (pos[3][n], quat[4][n] or None)."""
     rng = np.random.default_rng(seed)
     rc = circumradius(kind, params)
     k = int(math.ceil(n ** (1.0 / 3.0) - 1e-9))
@@ -82,8 +120,18 @@ def lattice_state(n: int, L: float, kind: int, params, seed: int):
         pos = np.stack([(ix + 0.5) * sp, (iy + 0.5) * sp, (iz + 0.5) * sp]).astype(np.float64)
         quat = random_quaternions(n, rng) if oriented else None
         return pos, quat
-    if kind != DISCOID:
-        raise ValueError("density too high for an overlap-free cubic lattice")
+    if kind == SPHERE:
+        return cubic_sites(n, L, 2.0 * rc), None
+    if kind == HEMISPHERE:
+        gap = 1e-3 * 2.0 * rc
+        npair = (n + 1) // 2
+        centre = cubic_sites(npair, L, 2.0 * rc + gap)
+        qa = random_quaternions(npair, rng)
+        w, x, y, z = qa
+        axis = np.stack([2.0 * (x * z + w * y), 2.0 * (y * z - w * x), 1.0 - 2.0 * (x * x + y * y)])
+        pos = np.concatenate([centre + 0.5 * gap * axis, centre - 0.5 * gap * axis], axis=1)[:, :n]
+        quat = np.concatenate([qa, _flip_quaternions(qa)], axis=1)[:, :n]
+        return np.mod(pos, L), np.ascontiguousarray(quat)
     a, r = params
     # aligned disks (normal along z): in-plane spacing > 2(a + r), vertical spacing > 2 r
     nxy = int(math.floor(L / (2.0 * (a + r) * (1.0 + 1e-6))))
@@ -147,7 +195,7 @@ def c1_spheres_small(n_trial: int = 0) -> StatePoint:
 
 def c2_hemispheres(eta_r: float = 0.2, n: int = 16384) -> StatePoint:
     """Hemispheres d=1, N=16384, phi_c=0.20, q=0.15, eta_r in 0.1..0.4, translate+rotate."""
-    d_trans = {0.1: 0.04, 0.2: 0.02, 0.3: 0.013, 0.4: 0.01}.get(round(eta_r, 2), 0.02)
+    d_trans = {0.1: 0.1, 0.2: 0.07, 0.3: 0.045, 0.4: 0.035}.get(round(eta_r, 2), 0.05)
     return StatePoint(HEMISPHERE, (1.0,), n, 0.20, 0.15, eta_r, n_trial=0, d_trans=d_trans,
                       a_rot=d_trans, p_rot=0.5, seed=1,
                       name=f"hemispheres N={n} phi_c=0.20 q=0.15 eta_r={eta_r}")
@@ -193,6 +241,13 @@ def c5_request_stream(duration_s: float = 60.0, rate: float = 50.0, seed: int = 
         sp = StatePoint(kind, params, n, phi, q, eta, n_trial=0, d_trans=0.02,
                         a_rot=0.02 if kind != SPHERE else 0.0, p_rot=0.5 if kind != SPHERE else 0.0,
                         seed=seed * 100000 + i, replica_id=i, name=f"request {i}")
+        sp.extra["phi_requested"] = phi
+        while True:  # cap phi_c at what an overlap-free lattice start holds for this N
+            try:
+                sp.initial_state()
+                break
+            except ValueError:
+                sp.phi_c *= 0.98
         sp.extra["arrival_s"] = t
         sp.extra["sweeps"] = 100
         reqs.append(sp)
