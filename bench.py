@@ -40,6 +40,24 @@ VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 #   per depletant = 0.955 * (60 + 2 * 15) + 14 = 100.0 lane-instructions
 ALGO_OPS_PER_CHECK = 0.955 * (60 + 2 * 15) + 14
 
+# HBM bytes per launch of the sphere phase kernel, from two rocprofv3 passes
+# (FETCH_SIZE, WRITE_SIZE) scaled by the same counters over a plain 256 MiB
+# device copy; valid only for the kernel sources with this digest (otherwise
+# the roofline reports traffic null).
+PROFILED_KERNEL_DIGEST = "c34e00a875326089"
+PROFILED_TRAFFIC_BYTES = {"ball": 85633056, "shell": 86012009}
+
+
+def kernel_digest() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.hpp", "rng.hpp", "geom.hpp"):
+        with open(os.path.join(ROOT, "paper_1508_07077_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 # Shell insertion region: one candidate per block (60), 4 u32->f64 conversions
 # with their offsets and scalings (12), the disk test (3), the radius and its
 # r^2 test (5), 2 sqrt(1 - s) + direction + 3 scalings (16): 96 per block,
@@ -208,7 +226,8 @@ def main():
             "peak": VALU_PEAK_LANE_OPS / 1e12,
             "unit": "T VALU lane-instr/s",
             "frac": achieved / VALU_PEAK_LANE_OPS,
-            "traffic": None,
+            "traffic": PROFILED_TRAFFIC_BYTES[args.v0] if kernel_digest() == PROFILED_KERNEL_DIGEST else None,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "avg_launch_ms": avg_phase_s * 1e3,
             "ops_per_check": ops_per_check,
         },
