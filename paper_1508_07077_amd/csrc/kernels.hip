@@ -56,6 +56,35 @@ __device__ inline int cell_of(const Params& P, double x, double y, double z, dou
 
 __device__ inline int lane_id() { return __lane_id(); }
 
+// periodic wrap of a cell coordinate that is at most one cell outside [0, n)
+__device__ inline int wrap1(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
+
+// this lane's offset in the de-duplicated cell stencil: 27 lanes over
+// {0, -1, +1}^3 (n > 2) or 8 lanes over {0, +1}^3 (n = 2); lane 0 is the cell
+// itself (divisions by the constant 3 only)
+struct NbOff {
+    int dx, dy, dz;
+    bool on;
+};
+__device__ inline NbOff nb_offset(int n)
+{
+    const int l = lane_id();
+    NbOff o;
+    if (n == 2) {
+        o.on = l < 8;
+        o.dx = l & 1;
+        o.dy = (l >> 1) & 1;
+        o.dz = (l >> 2) & 1;
+    } else {
+        o.on = l < 27;
+        int ix = l % 3, iy = (l / 3) % 3, iz = l / 9;
+        o.dx = ix == 1 ? -1 : (ix == 2 ? 1 : 0);
+        o.dy = iy == 1 ? -1 : (iy == 2 ? 1 : 0);
+        o.dz = iz == 1 ? -1 : (iz == 2 ? 1 : 0);
+    }
+    return o;
+}
+
 // number of set bits of `mask` in lanes below this one
 __device__ inline int bits_below(unsigned long long mask)
 {
@@ -546,8 +575,7 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
     const int gw = blockIdx.x * P.waves_per_block + wv;
     const int nwaves = gridDim.x * P.waves_per_block;
     const double g0 = W.grid[0], g1 = W.grid[1], g2 = W.grid[2];
-    const int noff = (P.n == 2) ? 2 : 3;
-    const int ncl = noff * noff * noff;
+    const NbOff nb = nb_offset(P.n);
 
     for (int a = gw; a < P.active_cells; a += nwaves) {
         const int ax = a % P.h, ay = (a / P.h) % P.h, az = a / (P.h * P.h);
@@ -567,14 +595,8 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
         }
         // stencil: the de-duplicated 27 (n > 2) or 8 (n = 2) cells around C
         int es = 0, ec = 0;
-        if (lane < ncl) {
-            int dx = lane % noff, dy = (lane / noff) % noff, dz = lane / (noff * noff);
-            if (noff == 3) {
-                dx -= 1;
-                dy -= 1;
-                dz -= 1;
-            }
-            int ex = (cx + dx + P.n) % P.n, ey = (cy + dy + P.n) % P.n, ez = (cz + dz + P.n) % P.n;
+        if (nb.on) {
+            int ex = wrap1(cx + nb.dx, P.n), ey = wrap1(cy + nb.dy, P.n), ez = wrap1(cz + nb.dz, P.n);
             int e = ex + P.n * (ey + P.n * ez);
             es = W.cell_start[e];
             ec = W.cell_start[e + 1] - es;
@@ -894,23 +916,15 @@ __device__ inline double4 stage_rec(const SphereStage& sb, int i)
     return make_double4(sb.recA[2 * i], sb.recA[2 * i + 1], sb.recB[2 * i], sb.recB[2 * i + 1]);
 }
 
-// neighbour-cell ranges of cell C (lane l < ncl holds the range of neighbour l;
-// neighbour 0 is C itself)
-__device__ inline void stencil_ranges(const Params& P, const Work& W, int C, int& es, int& ec)
+// neighbour-cell ranges of cell C at (cx, cy, cz): a lane with nb.on holds
+// the range of its neighbour (lane 0: C itself)
+__device__ inline void stencil_ranges(const Params& P, const Work& W, const NbOff& nb, int C, int cx, int cy, int cz,
+                                      int& es, int& ec)
 {
-    const int lane = lane_id();
-    const int noff = (P.n == 2) ? 2 : 3;
-    const int ncl = noff * noff * noff;
     es = 0;
     ec = 0;
-    if (C >= 0 && lane < ncl) {
-        // offsets ordered 0, -1, +1 (n > 2) or 0, +1 (n = 2): neighbour 0 is the cell itself
-        int ix = lane % noff, iy = (lane / noff) % noff, iz = lane / (noff * noff);
-        int dx = (noff == 3 && ix == 1) ? -1 : (ix == 2 ? 1 : ix);
-        int dy = (noff == 3 && iy == 1) ? -1 : (iy == 2 ? 1 : iy);
-        int dz = (noff == 3 && iz == 1) ? -1 : (iz == 2 ? 1 : iz);
-        int cx = C % P.n, cy = (C / P.n) % P.n, cz = C / (P.n * P.n);
-        int e = (cx + dx + P.n) % P.n + P.n * ((cy + dy + P.n) % P.n + P.n * ((cz + dz + P.n) % P.n));
+    if (C >= 0 && nb.on) {
+        int e = wrap1(cx + nb.dx, P.n) + P.n * (wrap1(cy + nb.dy, P.n) + P.n * wrap1(cz + nb.dz, P.n));
         es = W.cell_start[e];
         ec = W.cell_start[e + 1] - es;
     }
@@ -979,18 +993,32 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
     const Mat3 Rnone{};
 
     // the chunk: lane k < kChunk holds active cell gw * kChunk + k
-    int Ck = -1, startk = 0, nck = 0;
+    int Ck = -1, startk = 0, nck = 0, cxk = 0, cyk = 0, czk = 0;
     {
         int a = gw * kChunk + lane;
         if (lane < kChunk && a < P.active_cells) {
             int ax = a % P.h, ay = (a / P.h) % P.h, az = a / (P.h * P.h);
-            int cx = 2 * ax + (colour & 1), cy = 2 * ay + ((colour >> 1) & 1), cz = 2 * az + ((colour >> 2) & 1);
-            Ck = cx + P.n * (cy + P.n * cz);
+            cxk = 2 * ax + (colour & 1);
+            cyk = 2 * ay + ((colour >> 1) & 1);
+            czk = 2 * az + ((colour >> 2) & 1);
+            Ck = cxk + P.n * (cyk + P.n * czk);
             startk = W.cell_start[Ck];
             nck = W.cell_start[Ck + 1] - startk;
         }
     }
     unsigned long long todo = __ballot(nck > 0);
+    const NbOff nb = nb_offset(P.n);
+    // ranges of the stencil of chunk cell k (k < 0: none)
+    auto ranges_of = [&](int k, int& es, int& ec) {
+        if (k < 0) {
+            stencil_ranges(P, W, nb, -1, 0, 0, 0, es, ec);
+            return;
+        }
+        stencil_ranges(P, W, nb, static_cast<int>(rdlane_u(static_cast<uint32_t>(Ck), k)),
+                       static_cast<int>(rdlane_u(static_cast<uint32_t>(cxk), k)),
+                       static_cast<int>(rdlane_u(static_cast<uint32_t>(cyk), k)),
+                       static_cast<int>(rdlane_u(static_cast<uint32_t>(czk), k)), es, ec);
+    };
     // pipeline: ranges two cells ahead, records one cell ahead
     auto next_cell = [&](unsigned long long& m) -> int {
         if (!m) return -1;
@@ -1002,9 +1030,9 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
     int kc = next_cell(rem);   // cell being processed
     int kn = next_cell(rem);   // next
     int es, ec;
-    stencil_ranges(P, W, kc >= 0 ? static_cast<int>(rdlane_u(static_cast<uint32_t>(Ck), kc)) : -1, es, ec);
+    ranges_of(kc, es, ec);
     int nst_cur = (kc >= 0) ? stage_issue(P, W, stage_buf(0), es, ec) : 0;
-    stencil_ranges(P, W, kn >= 0 ? static_cast<int>(rdlane_u(static_cast<uint32_t>(Ck), kn)) : -1, es, ec);
+    ranges_of(kn, es, ec);
     int buf = 0;
 
     while (kc >= 0) {
@@ -1020,7 +1048,7 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
         int nst_next = 0;
         if (kn >= 0) {
             nst_next = stage_issue(P, W, stage_buf(buf ^ 1), es, ec);
-            stencil_ranges(P, W, kn2 >= 0 ? static_cast<int>(rdlane_u(static_cast<uint32_t>(Ck), kn2)) : -1, es, ec);
+            ranges_of(kn2, es, ec);
         }
         if (nst < 0 || nc > kStage) {
             if (lane == 0) atomicOr(W.flags, kFlagListOverflow);

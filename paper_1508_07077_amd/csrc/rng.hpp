@@ -34,25 +34,34 @@ struct Words {
 };
 
 // one 32x32 -> 64 multiply gives both halves (v_mad_u64_u32)
-__host__ __device__ inline void mulhilo(uint32_t a, uint32_t b, uint32_t& hi, uint32_t& lo)
+__device__ inline void mulhilo(uint32_t a, uint32_t b, uint32_t& hi, uint32_t& lo)
 {
     uint64_t p = static_cast<uint64_t>(a) * static_cast<uint64_t>(b);
     hi = static_cast<uint32_t>(p >> 32);
     lo = static_cast<uint32_t>(p);
 }
 
-__host__ __device__ inline Words philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1)
+// a ^ b ^ k in one VALU instruction (three-input bit operation, truth table
+// 0x96 = odd parity); the round key k is wave-uniform
+__device__ inline uint32_t xor3(uint32_t a, uint32_t b, uint32_t k)
+{
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+    return r;
+}
+
+// Philox4x32-10 (Salmon et al., SC'11): per round two 32x32->64 multiplies
+// and two three-way XORs; the key schedule stays in scalar registers
+__device__ inline Words philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         uint32_t hi0, lo0, hi1, lo1;
         mulhilo(0xD2511F53u, c0, hi0, lo0);
         mulhilo(0xCD9E8D57u, c2, hi1, lo1);
-        uint32_t n0 = hi1 ^ c1 ^ k0;
-        uint32_t n2 = hi0 ^ c3 ^ k1;
-        c0 = n0;
+        c0 = xor3(hi1, c1, k0);
         c1 = lo1;
-        c2 = n2;
+        c2 = xor3(hi0, c3, k1);
         c3 = lo0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
@@ -70,12 +79,8 @@ __host__ __device__ inline double u52(uint32_t w0, uint32_t w1)
     return (static_cast<double>(k) + 0.5) * 0x1p-52;
 }
 
-// (2w + 1 - 2^32) 2^-32 in (-1, 1), exact
-__host__ __device__ inline double sym01(uint32_t w)
-{
-    int64_t odd = 2 * static_cast<int64_t>(w) + 1 - (static_cast<int64_t>(1) << 32);
-    return static_cast<double>(odd) * 0x1p-32;
-}
+// (2w + 1 - 2^32) 2^-32 in (-1, 1): (w + 1/2) 2^-31 - 1, every step exact
+__host__ __device__ inline double sym01(uint32_t w) { return (static_cast<double>(w) + 0.5) * 0x1p-31 - 1.0; }
 
 // multiply-shift choice in [0, n)
 __host__ __device__ inline uint32_t pick(uint32_t w, uint32_t n)
