@@ -191,6 +191,25 @@ def main():
         "acceptance": tot2["accepts"] / tot2["trials"],
         "depletants_per_move": tot2["depletants_drawn"] / tot2["trials"],
     }
+    # FP32 geometry with the FP64 guard band, same state point and region as the headline
+    s32 = hp.Sim(sp.n, sp.L, sp.seed, precision=hp.FP32_GUARDED)
+    s32.set_shape(hp.SPHERE, sp.params)
+    s32.set_fugacity(sp.z_p, sp.d_dep, sp.n_trial)
+    s32.set_moves(sp.d_trans)
+    s32.set_insertion(region)
+    s32.set_state(sim.pos.clone())
+    tot3, lat3, phase3, dt3 = _timed_sweeps(torch, s32, args.steps, args.warmup)
+    fp32 = {
+        "insertion_region": args.v0,
+        "moves_per_s": tot3["trials"] / dt3,
+        "depletant_checks_per_s": tot3["depletants_resolved"] / dt3,
+        "ms_per_step": dt3 * 1e3 / args.steps,
+        "avg_launch_ms": phase3 / launches,
+        "fp64_fallbacks": tot3["fp64_fallbacks"],
+        "fp64_fallbacks_per_depletant": tot3["fp64_fallbacks"] / max(tot3["depletants_drawn"], 1),
+        "note": "FP32 depletant tests with a 1e-5 sigma FP64 guard band; decisions equal to FP64",
+    }
+    s32.close()
     line = {
         "metric": "colloid trial moves/s + depletant overlap checks/s (1 GPU); p50/p99 latency",
         "value": moves,
@@ -232,6 +251,7 @@ def main():
             "ops_per_check": ops_per_check,
         },
         "other_insertion_region": companion,
+        "fp32_guarded": fp32,
     }
     if args.cpu_seconds > 0:
         line["cpu_baseline"] = cpu_baseline(lambda n: wl.c3_spheres_large(n=n, d_trans=sp.d_trans), args.cpu_n,

@@ -243,6 +243,13 @@ Params make_params(const hpmc_sim* s)
     P.shell = s->region == HPMC_V0_SHELL;
     P.r_inner = s->r_inner;
     P.span = s->span;
+    {
+        // sigma = the colloid's circumdiameter
+        double eps = 1e-5 * (2.0 * s->S.rcirc);
+        double lo = (s->R0 - eps) * (s->R0 - eps), hi = (s->R0 + eps) * (s->R0 + eps);
+        P.g_lo = nextafterf(static_cast<float>(lo), 0.0f);
+        P.g_hi = nextafterf(static_cast<float>(hi), INFINITY);
+    }
     // per-wave LDS of the phase kernel: rigorous packing bounds (hard bodies
     // are disjoint) for the stencil list and own-cell records
     double rc2 = 2.0 * s->S.rcirc;
@@ -289,6 +296,7 @@ Group make_group(const Desc* d, const hpmc_sim* const* sims, int n)
     g.d = d;
     g.nrep = n;
     g.kind = sims[0]->S.kind;
+    g.precision = sims[0]->precision;
     g.wpb = 4;
     size_t wave_lds = 0;
     for (int i = 0; i < n; ++i) {
@@ -709,19 +717,20 @@ int hpmc_sweep_batch(hpmc_sim* const* sims, int n_sims, void* batch_ws, size_t b
         if (sims[i]->trace) return fail(sims[i], HPMC_EINVAL, "tracing is per handle; disable it for batched sweeps");
     }
     hipStream_t st = sims[0]->stream;
-    // replicas that share a shape kind share each launch; groups run one after another
+    // replicas that share a shape kind and precision share each launch; groups run one after another
     Desc* d_all = static_cast<Desc*>(batch_ws);
     unsigned long long* d_gather = reinterpret_cast<unsigned long long*>(
         static_cast<unsigned char*>(batch_ws) + align256(static_cast<size_t>(n_sims) * sizeof(Desc)));
     std::vector<int> order;
-    for (int k = 0; k < 3; ++k)
+    auto cls = [&](int i) { return 2 * sims[i]->S.kind + sims[i]->precision; };
+    for (int k = 0; k < 6; ++k)
         for (int i = 0; i < n_sims; ++i)
-            if (sims[i]->S.kind == k) order.push_back(i);
+            if (cls(i) == k) order.push_back(i);
     std::vector<Desc> host(static_cast<size_t>(n_sims));
     std::vector<Group> groups;
     for (size_t b = 0; b < order.size();) {
         size_t e = b;
-        while (e < order.size() && sims[order[e]]->S.kind == sims[order[b]]->S.kind) ++e;
+        while (e < order.size() && cls(order[e]) == cls(order[b])) ++e;
         std::vector<const hpmc_sim*> members;
         for (size_t q = b; q < e; ++q) members.push_back(sims[order[q]]);
         Group g = make_group(d_all + b, members.data(), static_cast<int>(members.size()));

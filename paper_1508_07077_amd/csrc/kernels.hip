@@ -905,6 +905,29 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
 // ---------------------------------------------------------------------------
 constexpr int kStage = 64;  // staged stencil entries per cell (more are read from HBM)
 
+// Is the point at offset a - b within R0 of the centre?  FP64 (the contract)
+// or, in the guarded mode, FP32 with a band of 1e-5 sigma around R0: outside
+// the band the FP32 decision equals the FP64 one (its rounding error is below
+// 1e-6 where |a - b| is near R0, the band is 1.1e-5 wide in |a - b|^2), inside it
+// the FP64 test decides and the fallback is counted.
+template <bool F32>
+__device__ inline bool sphere_in(const Params& P, Vec3 a, Vec3 b, bool active, unsigned long long& fallbacks)
+{
+    if constexpr (!F32) return dot(a - b, a - b) < P.S.R0sq;
+    float vx = static_cast<float>(a.x) - static_cast<float>(b.x);
+    float vy = static_cast<float>(a.y) - static_cast<float>(b.y);
+    float vz = static_cast<float>(a.z) - static_cast<float>(b.z);
+    float q = (vx * vx + vy * vy) + vz * vz;
+    bool in = q < P.g_lo;
+    bool amb = active && !in && !(q > P.g_hi);
+    unsigned long long m = __ballot(amb);
+    if (m) {
+        fallbacks += static_cast<unsigned long long>(__popcll(m));
+        if (amb) in = dot(a - b, a - b) < P.S.R0sq;
+    }
+    return in;
+}
+
 struct SphereStage {
     int* list;      // stencil slots (list_cap)
     double* recA;   // entry i: (x, y) at [2i, 2i + 1]
@@ -964,6 +987,7 @@ __device__ inline bool sphere_hit_lane(const Params& P, const Work& W, const Sph
     return hit && active;
 }
 
+template <bool F32>
 __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W, int phase)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1131,8 +1155,9 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
                             uint32_t k0 = kbase + static_cast<uint32_t>(bits_below(m0) + bits_below(m1));
                             uint32_t k1 = k0 + (acc0 ? 1u : 0u);
                             // ignored by the old pose (every ball point overlaps the new pose)
-                            bool v0 = acc0 && k0 < Np && !(dot(e0 - Dold, e0 - Dold) < P.S.R0sq);
-                            bool v1 = acc1 && k1 < Np && !(dot(e1 - Dold, e1 - Dold) < P.S.R0sq);
+                            bool v0 = acc0 && k0 < Np, v1 = acc1 && k1 < Np;
+                            v0 = v0 && !sphere_in<F32>(P, e0, Dold, v0, cnt[cFp64Fallbacks]);
+                            v1 = v1 && !sphere_in<F32>(P, e1, Dold, v1, cnt[cFp64Fallbacks]);
                             unsigned long long r0 = __ballot(v0), r1 = __ballot(v1);
                             while ((r0 | r1) && !done) {
                                 int l0 = r0 ? ffs64(r0) : 64, l1 = r1 ? ffs64(r1) : 64;
@@ -1150,7 +1175,7 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
                                 Vec3 es3 = cand ? e1 : e0;
                                 es3 = v3(rdlane_d(es3.x, src), rdlane_d(es3.y, src), rdlane_d(es3.z, src));
                                 uint32_t ks = rdlane_u(cand ? k1 : k0, src);
-                                bool h = dot(es3 - Dreg, es3 - Dreg) < P.S.R0sq;
+                                bool h = sphere_in<F32>(P, es3, Dreg, true, cnt[cFp64Fallbacks]);
                                 for (int i = kStage + lane; i < nst; i += 64) {
                                     double4 r = W.rpos[S0.list[i]];
                                     Vec3 D = v3(mi(P, r.x - xn.x), mi(P, r.y - xn.y), mi(P, r.z - xn.z));
@@ -1273,13 +1298,15 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
 #ifndef HPMC_SPHERE_WAVES_PER_EU
 #define HPMC_SPHERE_WAVES_PER_EU 3
 #endif
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HPMC_SPHERE_WAVES_PER_EU, 8))) void
+// F32: depletant tests in FP32 with the FP64 guard band (precision HPMC_FP32_GUARDED)
+template <bool F32>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F32 ? 2 : HPMC_SPHERE_WAVES_PER_EU, 8))) void
 phase_sphere_kernel(const Desc* __restrict__ D, int phase)
 {
     Params P = D[blockIdx.y].P;
     const Work W = D[blockIdx.y].W;
     P.sweep = *W.sweep_dev;
-    phase_sphere_body(P, W, phase);
+    phase_sphere_body<F32>(P, W, phase);
 }
 
 template <int KIND>
@@ -1553,7 +1580,12 @@ hipError_t launch_phase(const Group& g, int phase, hipStream_t stream)
     dim3 bs(64 * g.wpb);
     if (g.kind == kSphere) {
         int waves = blocks_for(g.maxActive, kChunk);
-        hipLaunchKernelGGL(phase_sphere_kernel, dim3(blocks_for(waves, g.wpb), R), bs, g.lds, stream, g.d, phase);
+        if (g.precision == 1)
+            hipLaunchKernelGGL(phase_sphere_kernel<true>, dim3(blocks_for(waves, g.wpb), R), bs, g.lds, stream, g.d,
+                               phase);
+        else
+            hipLaunchKernelGGL(phase_sphere_kernel<false>, dim3(blocks_for(waves, g.wpb), R), bs, g.lds, stream, g.d,
+                               phase);
     } else {
         int waves = g.maxActive < 256 * 32 ? g.maxActive : 256 * 32;
         if (R > 1 && waves > 512) waves = 512;

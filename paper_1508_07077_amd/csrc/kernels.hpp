@@ -54,6 +54,7 @@ struct Params {
     double s_ball;  // R0 * 2^-21
     int shell;      // depletants in the shell r_inner <= |e| < R0 instead of the ball
     double r_inner, span;  // span = R0 - r_inner
+    float g_lo, g_hi;      // FP32 guard band: (R0 - eps)^2 rounded down, (R0 + eps)^2 rounded up, eps = 1e-5 sigma
     // per-wave LDS layout of the phase kernel
     int list_cap, own_cap, geo_cap;
     int wave_lds;       // bytes per wave
@@ -95,6 +96,7 @@ struct Group {
     const Desc* d;  // device array of nrep descriptors
     int nrep;
     int kind;
+    int precision;  // 0 FP64, 1 FP32 with the FP64 guard band (sphere depletant tests)
     int maxN, maxCells, maxActive;
     int wpb;        // waves per block of the phase kernel (common to the group)
     size_t lds;     // dynamic LDS bytes of the phase kernel (common to the group)
