@@ -82,6 +82,8 @@ def parse():
                          "c5: Poisson request stream served with continuous batching")
     ap.add_argument("--v0", default="ball", choices=["ball", "shell"],
                     help="c3: depletant insertion region of the headline run (the other one is timed after it)")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="skip the launch-shape autotuner (default: tune before timing)")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="c5: length of the arrival trace")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (scales the HBM byte counters)")
@@ -167,6 +169,7 @@ def main():
     region = hp.V0_SHELL if args.v0 == "shell" else hp.V0_BALL
     sim.set_insertion(region)
     sim.ensure_workspace()
+    tuning = sim.autotune(sweeps=2) if args.autotune else None
     tot, lat, phase_ms, dt = _timed_sweeps(torch, sim, args.steps, args.warmup)
     moves = tot["trials"] / dt
     checks = tot["depletants_resolved"] / dt
@@ -252,6 +255,7 @@ def main():
         },
         "other_insertion_region": companion,
         "fp32_guarded": fp32,
+        "launch_tuning": tuning,
     }
     if args.cpu_seconds > 0:
         line["cpu_baseline"] = cpu_baseline(lambda n: wl.c3_spheres_large(n=n, d_trans=sp.d_trans), args.cpu_n,
@@ -363,6 +367,7 @@ def bench_c2(args):
     for eta in (0.1, 0.2, 0.3, 0.4):
         sp = wl.c2_hemispheres(eta)
         sim = _make(hp, sp)
+        tuning = sim.autotune(sweeps=2) if args.autotune else None
         for _ in range(3):
             sim.sweep(1, counters=True)
         torch.cuda.synchronize()
@@ -376,7 +381,8 @@ def bench_c2(args):
         dt = time.perf_counter() - t0
         per[str(eta)] = {"moves_per_s": tot["trials"] / dt, "depletant_checks_per_s": tot["depletants_resolved"] / dt,
                          "acceptance": tot["accepts"] / tot["trials"], "ms_per_sweep": dt * 1e3 / args.steps,
-                         "z_p": sp.z_p, "delta": sp.d_trans, "near_contact_trials": tot["near_contact"]}
+                         "z_p": sp.z_p, "delta": sp.d_trans, "near_contact_trials": tot["near_contact"],
+                         "launch_tuning": tuning}
         moves += tot["trials"]
         checks += tot["depletants_resolved"]
         secs += dt
@@ -398,6 +404,13 @@ def bench_c4(args):
 
     sps = wl.c4_discoid_replicas()
     sims = [_make(hp, sp) for sp in sps]
+    tuning = None
+    if args.autotune:
+        # the batch launches with the shape of its first handle: tune the largest replica
+        big = max(sims, key=lambda x: x.n)
+        tuning = big.autotune(sweeps=2)
+        for x in sims:
+            x.set_tuning(tuning["cells_per_wave"], tuning["waves_per_block"], tuning["max_waves"])
     b = hp.Batch(sims)
     for _ in range(3):
         b.sweep(1, counters=True)
@@ -416,7 +429,7 @@ def bench_c4(args):
                  f"256 swept-disk replicas, N={sum(s.n for s in sps)} in total (128..8192 each), "
                  "phi_c U[0.05,0.45], eta_r U[0,0.5], q=0.2, one launch per kernel for all replicas",
                  {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                  "replicas": len(sps)})
+                  "replicas": len(sps), "launch_tuning": tuning})
 
 
 def bench_c5(args):

@@ -197,6 +197,33 @@ int hpmc_set_trace(hpmc_sim* sim, int enable);
  * Errors: ESTATE, ENOMEM, EHIP, ECAPACITY (checked when out is non-NULL). */
 int hpmc_sweep(hpmc_sim* sim, int n_sweeps, hpmc_counters* out);
 
+/* Launch shape of the phase kernels.  It never changes a result (every
+ * random draw is keyed by sweep, cell, round and purpose, not by thread), only
+ * the speed.  Zero fields mean the default. */
+typedef struct hpmc_tuning {
+    int32_t cells_per_wave;  /* spheres: active cells per wave, 1..64 (default 16) */
+    int32_t waves_per_block; /* 1, 2 or 4 (default 4; lowered to what the LDS holds) */
+    int32_t max_waves;       /* oriented shapes: waves of the grid-stride launch, >= 1 (default 8192) */
+    int32_t candidates;      /* hpmc_autotune: configurations timed */
+    double best_ms;          /* hpmc_autotune: phase-kernel ms per sweep of the chosen shape */
+    double default_ms;       /* hpmc_autotune: the same for the default shape */
+} hpmc_tuning;
+
+/* Set the launch shape explicitly (the last three fields are ignored).
+ * Batched sweeps use the shape of the first handle of each group.
+ * Errors: EINVAL (a field out of range). */
+int hpmc_set_tuning(hpmc_sim* sim, const hpmc_tuning* tuning);
+
+/* Autotuner: time candidate launch shapes (spheres: cells per wave in
+ * {4, 8, 16, 32, 64} x waves per block in {1, 2, 4}; oriented shapes: waves
+ * per block x wave count in {1024 .. 32768}) on a copy of the current state,
+ * `sweeps` timed sweeps each after one untimed, keep the fastest, and report
+ * it in *out (may be NULL).  The handle's state and sweep index are left as
+ * they were.  scratch: device memory of at least 8 N (3 + 4 if oriented)
+ * bytes, used only during the call.  Synchronises.  Errors: EINVAL, ESTATE,
+ * ENOMEM (scratch too small), EHIP, ECAPACITY. */
+int hpmc_autotune(hpmc_sim* sim, void* scratch, size_t scratch_bytes, int sweeps, hpmc_tuning* out);
+
 /* Device scratch needed by hpmc_sweep_batch for n_sims handles. */
 int hpmc_batch_workspace_bytes(int n_sims, size_t* bytes);
 

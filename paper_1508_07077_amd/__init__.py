@@ -49,6 +49,8 @@ EXPORTS = (
     "hpmc_trace",
     "hpmc_batch_workspace_bytes",
     "hpmc_sweep_batch",
+    "hpmc_set_tuning",
+    "hpmc_autotune",
 )
 
 COUNTERS = (
@@ -86,6 +88,17 @@ class HpmcError(RuntimeError):
 class _Counters(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint64) for f in COUNTERS] + [("phase_kernel_ms", ctypes.c_double),
                                                           ("sweep_ms", ctypes.c_double)]
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [
+        ("cells_per_wave", ctypes.c_int32),
+        ("waves_per_block", ctypes.c_int32),
+        ("max_waves", ctypes.c_int32),
+        ("candidates", ctypes.c_int32),
+        ("best_ms", ctypes.c_double),
+        ("default_ms", ctypes.c_double),
+    ]
 
 
 class _ObsParams(ctypes.Structure):
@@ -129,6 +142,8 @@ def lib():
         L.hpmc_trace.argtypes = [vp, vp, i64, ctypes.POINTER(i64)]
         L.hpmc_batch_workspace_bytes.argtypes = [cint, ctypes.POINTER(ctypes.c_size_t)]
         L.hpmc_sweep_batch.argtypes = [ctypes.POINTER(vp), cint, vp, ctypes.c_size_t, cint, ctypes.POINTER(_Counters)]
+        L.hpmc_set_tuning.argtypes = [vp, ctypes.POINTER(_Tuning)]
+        L.hpmc_autotune.argtypes = [vp, vp, ctypes.c_size_t, cint, ctypes.POINTER(_Tuning)]
         for name in EXPORTS:
             if name not in ("hpmc_destroy", "hpmc_last_error"):
                 getattr(L, name).restype = cint
@@ -242,6 +257,21 @@ class Sim:
             d["sweep_ms"] = float(c.sweep_ms)
             return d
         return None
+
+    def set_tuning(self, cells_per_wave: int = 0, waves_per_block: int = 0, max_waves: int = 0):
+        """Launch shape of the phase kernels (0 = default); results never depend on it."""
+        t = _Tuning(int(cells_per_wave), int(waves_per_block), int(max_waves), 0, 0.0, 0.0)
+        self._chk(lib().hpmc_set_tuning(self._h, ctypes.byref(t)), "set_tuning")
+
+    def autotune(self, sweeps: int = 2) -> dict:
+        """Time candidate launch shapes on a copy of the state and keep the fastest."""
+        n = self.n * (3 + (4 if self.quat is not None else 0))
+        scratch = self.torch.empty(n, dtype=self.torch.float64, device=self.device)
+        t = _Tuning()
+        self._chk(lib().hpmc_autotune(self._h, ctypes.c_void_p(scratch.data_ptr()), scratch.numel() * 8, int(sweeps),
+                                      ctypes.byref(t)), "autotune")
+        del scratch
+        return {f: getattr(t, f) for f, _ in _Tuning._fields_}
 
     def trace(self) -> np.ndarray:
         cap = self.n * 1024

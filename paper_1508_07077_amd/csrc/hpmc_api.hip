@@ -37,6 +37,8 @@ struct hpmc_sim {
     double d_trans = 0.1, a_rot = 0, p_rot = 0;
     int n_select = 1;
     int region = HPMC_V0_BALL;
+    // launch shape (results do not depend on it): 0 = default
+    int tune_chunk = 0, tune_wpb = 0, tune_waves = 0;
     // derived
     int n = 0;
     double w = 0, inv_w = 0, R0 = 0, lambda = 0, lambda_c = 0, s_ball = 0;
@@ -270,9 +272,10 @@ Params make_params(const hpmc_sim* s)
         P.off_geo = 0;
         P.wave_lds = static_cast<int>(2 * o);
         P.own_cap = 64;
-        int wpb = 4;
+        int wpb = s->tune_wpb ? s->tune_wpb : 4;
         while (wpb > 1 && kTableLds + static_cast<size_t>(wpb) * P.wave_lds > 64 * 1024) wpb >>= 1;
         P.waves_per_block = wpb;
+        P.chunk = s->tune_chunk ? s->tune_chunk : kChunk;
         return P;
     }
     size_t off = align256(static_cast<size_t>(list_cap) * 4);
@@ -283,9 +286,10 @@ Params make_params(const hpmc_sim* s)
     P.off_geo = static_cast<int>(off);
     off = align256(off + static_cast<size_t>(geo_cap) * 8 * gs);
     P.wave_lds = static_cast<int>(off);
-    int wpb = 4;
+    int wpb = s->tune_wpb ? s->tune_wpb : 4;
     while (wpb > 1 && kTableLds + static_cast<size_t>(wpb) * off > 64 * 1024) wpb >>= 1;
     P.waves_per_block = wpb;
+    P.chunk = kChunk;
     return P;
 }
 
@@ -298,6 +302,8 @@ Group make_group(const Desc* d, const hpmc_sim* const* sims, int n)
     g.kind = sims[0]->S.kind;
     g.precision = sims[0]->precision;
     g.wpb = 4;
+    g.chunk = sims[0]->tune_chunk ? sims[0]->tune_chunk : kChunk;
+    g.max_waves = sims[0]->tune_waves ? sims[0]->tune_waves : kMaxWaves;
     size_t wave_lds = 0;
     for (int i = 0; i < n; ++i) {
         Params P = make_params(sims[i]);
@@ -311,11 +317,12 @@ Group make_group(const Desc* d, const hpmc_sim* const* sims, int n)
     return g;
 }
 
-Desc make_desc(const hpmc_sim* s, int wpb)
+Desc make_desc(const hpmc_sim* s, int wpb, int chunk)
 {
     Desc d{};
     d.P = make_params(s);
     d.P.waves_per_block = wpb;
+    d.P.chunk = chunk;
     d.W = s->W;
     return d;
 }
@@ -323,7 +330,8 @@ Desc make_desc(const hpmc_sim* s, int wpb)
 // refresh the device descriptor of a single handle when its host copy changed
 int sync_desc(hpmc_sim* s)
 {
-    Desc d = make_desc(s, make_params(s).waves_per_block);
+    Params P = make_params(s);
+    Desc d = make_desc(s, P.waves_per_block, P.chunk);
     if (!s->desc_dirty && memcmp(&d, &s->desc, sizeof(Desc)) == 0) return HPMC_OK;
     s->desc = d;
     hipError_t e = hipMemcpyAsync(s->d_desc, &s->desc, sizeof(Desc), hipMemcpyHostToDevice, s->stream);
@@ -691,6 +699,105 @@ int hpmc_sweep(hpmc_sim* s, int n_sweeps, hpmc_counters* out)
     return HPMC_OK;
 }
 
+int hpmc_set_tuning(hpmc_sim* s, const hpmc_tuning* t)
+{
+    if (!s) return HPMC_EINVAL;
+    if (!t) return fail(s, HPMC_EINVAL, "null tuning");
+    if (t->cells_per_wave < 0 || t->cells_per_wave > 64 || t->max_waves < 0 ||
+        !(t->waves_per_block == 0 || t->waves_per_block == 1 || t->waves_per_block == 2 || t->waves_per_block == 4))
+        return fail(s, HPMC_EINVAL, "launch shape out of range");
+    s->tune_chunk = t->cells_per_wave;
+    s->tune_wpb = t->waves_per_block;
+    s->tune_waves = t->max_waves;
+    s->desc_dirty = 1;
+    return HPMC_OK;
+}
+
+int hpmc_autotune(hpmc_sim* s, void* scratch, size_t bytes, int sweeps, hpmc_tuning* out)
+{
+    if (!s) return HPMC_EINVAL;
+    if (!scratch || sweeps < 1 || sweeps > 64) return fail(s, HPMC_EINVAL, "autotune needs scratch and 1..64 sweeps");
+    int r = check_ready(s, true);
+    if (r != HPMC_OK) return r;
+    const size_t N = static_cast<size_t>(s->N);
+    const size_t need = N * 3 * sizeof(double) + (s->S.oriented ? N * 4 * sizeof(double) : 0);
+    if (bytes < need) return fail(s, HPMC_ENOMEM, "autotune scratch smaller than the state");
+    // candidates
+    std::vector<hpmc_tuning> cand;
+    if (!s->S.oriented) {
+        for (int c : {16, 4, 8, 32, 64})
+            for (int w : {4, 2, 1}) cand.push_back(hpmc_tuning{c, w, 0, 0, 0.0, 0.0});
+    } else {
+        for (int m : {kMaxWaves, 1024, 2048, 4096, 16384, 32768})
+            for (int w : {4, 2, 1}) cand.push_back(hpmc_tuning{0, w, m, 0, 0.0, 0.0});
+    }
+    // run on a copy of the state; restore everything afterwards
+    double* pos0 = s->pos;
+    double* quat0 = s->quat;
+    const uint64_t sweep0 = s->sweep;
+    const int trace0 = s->trace;
+    const int c0 = s->tune_chunk, w0 = s->tune_wpb, m0 = s->tune_waves;
+    double* spos = static_cast<double*>(scratch);
+    double* squat = s->S.oriented ? spos + 3 * N : nullptr;
+    hipError_t e = hipMemcpyAsync(spos, pos0, N * 3 * sizeof(double), hipMemcpyDeviceToDevice, s->stream);
+    if (e == hipSuccess && squat)
+        e = hipMemcpyAsync(squat, quat0, N * 4 * sizeof(double), hipMemcpyDeviceToDevice, s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "autotune copy");
+    s->pos = spos;
+    s->quat = squat;
+    s->W.pos = spos;
+    s->W.quat = squat;
+    s->trace = 0;
+    s->desc_dirty = 1;
+    int best = -1;
+    double best_ms = 0.0, default_ms = 0.0;
+    for (size_t i = 0; i < cand.size() && r == HPMC_OK; ++i) {
+        s->tune_chunk = cand[i].cells_per_wave;
+        s->tune_wpb = cand[i].waves_per_block;
+        s->tune_waves = cand[i].max_waves;
+        s->desc_dirty = 1;
+        hpmc_counters c{};
+        r = hpmc_sweep(s, 1, &c);
+        if (r == HPMC_OK) r = hpmc_sweep(s, sweeps, &c);
+        if (r != HPMC_OK) break;
+        double ms = c.phase_kernel_ms / sweeps;
+        if (i == 0) default_ms = ms;
+        if (best < 0 || ms < best_ms) {
+            best = static_cast<int>(i);
+            best_ms = ms;
+        }
+    }
+    // restore the state pointers, the sweep index and its device copy
+    s->pos = pos0;
+    s->quat = quat0;
+    s->W.pos = pos0;
+    s->W.quat = quat0;
+    s->trace = trace0;
+    s->trace_valid = 0;
+    s->sweep = sweep0;
+    s->desc_dirty = 1;
+    int r2 = set_sweep_dev(s);
+    if (r == HPMC_OK && r2 != HPMC_OK) r = r2;
+    e = hipStreamSynchronize(s->stream);
+    if (r == HPMC_OK && e != hipSuccess) r = hip_fail(s, e, "autotune");
+    if (r != HPMC_OK) {
+        s->tune_chunk = c0;
+        s->tune_wpb = w0;
+        s->tune_waves = m0;
+        return r;
+    }
+    s->tune_chunk = cand[best].cells_per_wave;
+    s->tune_wpb = cand[best].waves_per_block;
+    s->tune_waves = cand[best].max_waves;
+    if (out) {
+        *out = cand[best];
+        out->candidates = static_cast<int32_t>(cand.size());
+        out->best_ms = best_ms;
+        out->default_ms = default_ms;
+    }
+    return HPMC_OK;
+}
+
 int hpmc_batch_workspace_bytes(int n_sims, size_t* bytes)
 {
     if (n_sims < 1 || !bytes) return HPMC_EINVAL;
@@ -734,7 +841,7 @@ int hpmc_sweep_batch(hpmc_sim* const* sims, int n_sims, void* batch_ws, size_t b
         std::vector<const hpmc_sim*> members;
         for (size_t q = b; q < e; ++q) members.push_back(sims[order[q]]);
         Group g = make_group(d_all + b, members.data(), static_cast<int>(members.size()));
-        for (size_t q = b; q < e; ++q) host[q] = make_desc(sims[order[q]], g.wpb);
+        for (size_t q = b; q < e; ++q) host[q] = make_desc(sims[order[q]], g.wpb, g.chunk);
         groups.push_back(g);
         b = e;
     }

@@ -897,7 +897,7 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
 }
 
 // ---------------------------------------------------------------------------
-// Spheres: one wave per chunk of kChunk active cells.  The stencil records of
+// Spheres: one wave per chunk of P.chunk active cells.  The stencil records of
 // a cell (its own members first, then the 26 neighbour cells) are staged in
 // LDS by direct global->LDS loads issued while the previous non-empty cell of
 // the chunk runs its trials; neighbour ranges two cells ahead are loaded into
@@ -1016,11 +1016,11 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
     const double g0 = W.grid[0], g1 = W.grid[1], g2 = W.grid[2];
     const Mat3 Rnone{};
 
-    // the chunk: lane k < kChunk holds active cell gw * kChunk + k
+    // the chunk: lane k < P.chunk holds active cell gw * P.chunk + k
     int Ck = -1, startk = 0, nck = 0, cxk = 0, cyk = 0, czk = 0;
     {
-        int a = gw * kChunk + lane;
-        if (lane < kChunk && a < P.active_cells) {
+        int a = gw * P.chunk + lane;
+        if (lane < P.chunk && a < P.active_cells) {
             int ax = a % P.h, ay = (a / P.h) % P.h, az = a / (P.h * P.h);
             cxk = 2 * ax + (colour & 1);
             cyk = 2 * ay + ((colour >> 1) & 1);
@@ -1579,7 +1579,7 @@ hipError_t launch_phase(const Group& g, int phase, hipStream_t stream)
     const int R = g.nrep;
     dim3 bs(64 * g.wpb);
     if (g.kind == kSphere) {
-        int waves = blocks_for(g.maxActive, kChunk);
+        int waves = blocks_for(g.maxActive, g.chunk);
         if (g.precision == 1)
             hipLaunchKernelGGL(phase_sphere_kernel<true>, dim3(blocks_for(waves, g.wpb), R), bs, g.lds, stream, g.d,
                                phase);
@@ -1587,7 +1587,7 @@ hipError_t launch_phase(const Group& g, int phase, hipStream_t stream)
             hipLaunchKernelGGL(phase_sphere_kernel<false>, dim3(blocks_for(waves, g.wpb), R), bs, g.lds, stream, g.d,
                                phase);
     } else {
-        int waves = g.maxActive < 256 * 32 ? g.maxActive : 256 * 32;
+        int waves = g.maxActive < g.max_waves ? g.maxActive : g.max_waves;
         if (R > 1 && waves > 512) waves = 512;
         dim3 grid(blocks_for(waves, g.wpb), R);
         if (g.kind == kHemisphere)

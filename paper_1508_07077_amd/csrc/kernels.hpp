@@ -60,6 +60,7 @@ struct Params {
     int wave_lds;       // bytes per wave
     int off_own_pos, off_own_q, off_geo;
     int waves_per_block;
+    int chunk;          // spheres: active cells per wave (1..64)
     int active_cells;   // h^3
 };
 
@@ -99,6 +100,8 @@ struct Group {
     int precision;  // 0 FP64, 1 FP32 with the FP64 guard band (sphere depletant tests)
     int maxN, maxCells, maxActive;
     int wpb;        // waves per block of the phase kernel (common to the group)
+    int chunk;      // spheres: active cells per wave (common to the group)
+    int max_waves;  // oriented shapes: waves of the grid-stride phase launch
     size_t lds;     // dynamic LDS bytes of the phase kernel (common to the group)
 };
 
@@ -116,6 +119,7 @@ hipError_t launch_free_volume(const Group& g, int64_t n_probe, uint32_t seq, dou
                               hipStream_t stream);
 hipError_t launch_sdf(const Group& g, const Params& P, const Work& W, int n_bins, double x_max, hipStream_t stream);
 
-constexpr int kChunk = 16;  // active cells per wave of the sphere phase kernel
+constexpr int kChunk = 16;  // default active cells per wave of the sphere phase kernel
+constexpr int kMaxWaves = 256 * 32;  // default wave count of the oriented phase launch
 
 }  // namespace hpmc
