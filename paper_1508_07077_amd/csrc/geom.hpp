@@ -233,6 +233,51 @@ __host__ __device__ inline PairResult mpr_overlap(const Shape& S, Vec3 d, const 
     return res;
 }
 
+// Support value max_{x in shape} u.x of a body (reference point at the
+// origin, body z axis nz in world coordinates) along the unit vector u.
+__host__ __device__ inline double support_value(const Shape& S, Vec3 nz, Vec3 u)
+{
+    double c = dot(nz, u);
+    double s2 = 1.0 - c * c;
+    double rim = S.a * sqrt(s2 > 0.0 ? s2 : 0.0);
+    if (S.kind == kHemisphere) return c >= 0.0 ? S.a : rim;
+    return rim + S.rs;
+}
+
+// Separating-axis test of two oriented bodies (A at the origin, B at offset d)
+// along the centre line, both body axes and their cross product.  True only
+// when one axis separates them by more than 2e-9, so the bodies are then
+// disjoint and farther apart than any contact tolerance: every exact test
+// (MPR here, GJK in the oracle) reports no overlap for them.
+__host__ __device__ inline bool sat_axis_separates(const Shape& S, Vec3 na, Vec3 nb, Vec3 d, Vec3 u)
+{
+    const double margin = 2e-9;
+    Vec3 mu = neg(u);
+    double sd = dot(u, d);
+    // B beyond A along u, or along -u
+    return support_value(S, na, u) + support_value(S, nb, mu) + margin < sd ||
+           support_value(S, na, mu) + support_value(S, nb, u) + margin < -sd;
+}
+
+__host__ __device__ inline bool sat_disjoint(const Shape& S, Vec3 d, const Mat3& RA, const Mat3& RB)
+{
+    Vec3 na = v3(RA.m[2], RA.m[5], RA.m[8]);
+    Vec3 nb = v3(RB.m[2], RB.m[5], RB.m[8]);
+    double dd = dot(d, d);
+    if (dd > 0.0) {
+        double inv = 1.0 / sqrt(dd);
+        if (sat_axis_separates(S, na, nb, d, v3(d.x * inv, d.y * inv, d.z * inv))) return true;
+    }
+    if (sat_axis_separates(S, na, nb, d, na) || sat_axis_separates(S, na, nb, d, nb)) return true;
+    Vec3 cr = cross(na, nb);
+    double cc = dot(cr, cr);
+    if (cc > 1e-12) {
+        double inv = 1.0 / sqrt(cc);
+        if (sat_axis_separates(S, na, nb, d, v3(cr.x * inv, cr.y * inv, cr.z * inv))) return true;
+    }
+    return false;
+}
+
 // compile-time shape dispatch for the hot loops
 template <int KIND>
 __host__ __device__ inline bool dep_ov(const Shape& S, Vec3 v, const Mat3& R)
@@ -261,6 +306,7 @@ __host__ __device__ inline PairResult pair_overlap(const Shape& S, Vec3 d, const
     double dd = dot(d, d);
     if (S.kind == kSphere) return PairResult{dd < S.dsq, false};
     if (dd >= S.lim_sq) return PairResult{false, false};
+    if (sat_disjoint(S, d, RA, RB)) return PairResult{false, false};
     return mpr_overlap(S, d, RA, RB);
 }
 
@@ -272,6 +318,7 @@ __host__ __device__ inline PairResult pair_ov(const Shape& S, Vec3 d, const Mat3
         return PairResult{dd < S.dsq, false};
     } else {
         if (dd >= S.lim_sq) return PairResult{false, false};
+        if (sat_disjoint(S, d, RA, RB)) return PairResult{false, false};
         return mpr_overlap(S, d, RA, RB);
     }
 }

@@ -1470,15 +1470,43 @@ __global__ __launch_bounds__(256) void free_volume_kernel(const Desc* __restrict
 
 // per-particle smallest compression of a neighbour separation at which the
 // pair overlaps (scale-distribution function); histogram in W.obs
+// Scale factor at which the pair (A at the origin, B at offset d) first
+// overlaps when the centre distance is compressed by (1 - x): bisection of
+// [0, x_max] in 40 steps (overlap grows monotonically with x).
+__device__ inline double sdf_bisect(const Shape& S, Vec3 d, const Mat3& RA, const Mat3& RB, double x_max, double lim)
+{
+    double lo = 0.0, hi = x_max;
+    for (int it = 0; it < 40; ++it) {
+        double mid = 0.5 * (lo + hi);
+        double fm = 1.0 - mid;
+        Vec3 dx3 = v3(d.x * fm, d.y * fm, d.z * fm);
+        bool ov = dot(dx3, dx3) < lim * lim && !sat_disjoint(S, dx3, RA, RB) && mpr_overlap(S, dx3, RA, RB).overlap;
+        if (ov)
+            hi = mid;
+        else
+            lo = mid;
+    }
+    return hi;
+}
+
+constexpr int kSdfCand = 16;  // candidate pairs per particle held for the bisection pass
+
+// Per particle (thread) the minimum compression factor over its neighbours,
+// histogrammed.  Spheres: closed form.  Convex shapes: a scan over the
+// neighbours keeps the pairs that overlap at the largest compression x_max,
+// then the lanes of a wave bisect their candidates together, so bisections
+// of different particles do not run one after another.
 __global__ __launch_bounds__(128) void sdf_kernel(const Desc* __restrict__ D, int n_bins, double x_max, int k)
 {
     HPMC_REPLICA(D);
+    __shared__ int cand_lds[128 * kSdfCand];
+    int* cand = cand_lds + threadIdx.x * kSdfCand;
     int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= P.N) return;
-    double4 a = W.rpos[s];
+    const bool live = s < P.N;
+    double4 a = live ? W.rpos[s] : make_double4(0.0, 0.0, 0.0, -1.0);
     int ia = static_cast<int>(a.w);
     Mat3 RA, RB;
-    if (P.S.oriented) {
+    if (P.S.oriented && live) {
         double4 q = W.rquat[s];
         RA = quat_to_mat(q.x, q.y, q.z, q.w);
     }
@@ -1486,9 +1514,11 @@ __global__ __launch_bounds__(128) void sdf_kernel(const Desc* __restrict__ D, in
     double lim_s = 2.0 * P.S.rcirc / (1.0 - x_max);
     double lim = 2.0 * P.S.rcirc;
     double xmin = x_max;
+    int ncand = 0;
+    bool overflow = false;
     int fx, fy, fz;
     int nx = axis_span(P.n, k, fx), ny = axis_span(P.n, k, fy), nz = axis_span(P.n, k, fz);
-    for (int dz = 0; dz < nz; ++dz)
+    for (int dz = 0; dz < nz && live; ++dz)
         for (int dy = 0; dy < ny; ++dy)
             for (int dx = 0; dx < nx; ++dx) {
                 int ex = (nx == P.n) ? dx : wrap_cell(cx + fx + dx, P.n);
@@ -1501,39 +1531,49 @@ __global__ __launch_bounds__(128) void sdf_kernel(const Desc* __restrict__ D, in
                     Vec3 d = v3(mi(P, b.x - a.x), mi(P, b.y - a.y), mi(P, b.z - a.z));
                     double dd = dot(d, d);
                     if (dd >= lim_s * lim_s) continue;
-                    double x;
                     if (P.S.kind == kSphere) {
                         double r = sqrt(dd);
-                        x = 1.0 - P.S.a * 2.0 / r;
+                        double x = 1.0 - P.S.a * 2.0 / r;
                         if (x > x_max) x = x_max;
-                    } else {
-                        if (P.S.oriented) {
-                            double4 qb = W.rquat[q];
-                            RB = quat_to_mat(qb.x, qb.y, qb.z, qb.w);
-                        }
-                        double f = 1.0 - x_max;
-                        Vec3 dm = v3(d.x * f, d.y * f, d.z * f);
-                        if (dot(dm, dm) >= lim * lim || !mpr_overlap(P.S, dm, RA, RB).overlap) {
-                            x = x_max;
-                        } else {
-                            double lo = 0.0, hi = x_max;
-                            for (int it = 0; it < 40; ++it) {
-                                double mid = 0.5 * (lo + hi);
-                                double fm = 1.0 - mid;
-                                Vec3 dx3 = v3(d.x * fm, d.y * fm, d.z * fm);
-                                bool ov = dot(dx3, dx3) < lim * lim && mpr_overlap(P.S, dx3, RA, RB).overlap;
-                                if (ov)
-                                    hi = mid;
-                                else
-                                    lo = mid;
-                            }
-                            x = hi;
-                        }
+                        if (x < xmin) xmin = x;
+                        continue;
                     }
-                    if (x < xmin) xmin = x;
+                    // keep the pair if it overlaps at the largest compression
+                    double4 qb = W.rquat[q];
+                    RB = quat_to_mat(qb.x, qb.y, qb.z, qb.w);
+                    double f = 1.0 - x_max;
+                    Vec3 dm = v3(d.x * f, d.y * f, d.z * f);
+                    if (dot(dm, dm) >= lim * lim || sat_disjoint(P.S, dm, RA, RB) ||
+                        !mpr_overlap(P.S, dm, RA, RB).overlap)
+                        continue;
+                    if (ncand < kSdfCand) {
+                        cand[ncand++] = q;
+                    } else {
+                        overflow = true;  // rare: bisect in place
+                        double x = sdf_bisect(P.S, d, RA, RB, x_max, lim);
+                        if (x < xmin) xmin = x;
+                    }
                 }
             }
-    if (xmin < x_max) {
+    (void)overflow;
+    // bisection pass: candidate c of every lane at the same time.  A pair that
+    // does not overlap at the current minimum cannot lower it (monotonicity).
+    for (int c = 0; c < ncand; ++c) {
+        int q = cand[c];
+        double4 b = W.rpos[q];
+        Vec3 d = v3(mi(P, b.x - a.x), mi(P, b.y - a.y), mi(P, b.z - a.z));
+        double4 qb = W.rquat[q];
+        RB = quat_to_mat(qb.x, qb.y, qb.z, qb.w);
+        if (xmin < x_max) {
+            double f = 1.0 - xmin;
+            Vec3 dm = v3(d.x * f, d.y * f, d.z * f);
+            if (dot(dm, dm) >= lim * lim || sat_disjoint(P.S, dm, RA, RB) || !mpr_overlap(P.S, dm, RA, RB).overlap)
+                continue;
+        }
+        double x = sdf_bisect(P.S, d, RA, RB, x_max, lim);
+        if (x < xmin) xmin = x;
+    }
+    if (live && xmin < x_max) {
         int bin = static_cast<int>(floor(xmin * (static_cast<double>(n_bins) / x_max)));
         if (bin < n_bins) atomicAdd(&W.obs[bin], 1ull);
     }
