@@ -129,8 +129,11 @@ typedef struct hpmc_obs_params {
 
 /* Create a handle for n colloids in a cubic periodic box of side box_L.
  * seed and replica_id key the counter-based random streams (Philox4x32-10);
- * precision is HPMC_FP64 or HPMC_FP32_GUARDED; hip_stream is a hipStream_t or
- * NULL.  Allocates host metadata only.  Errors: EINVAL. */
+ * precision is HPMC_FP64 or HPMC_FP32_GUARDED; hip_stream is the hipStream_t
+ * every call of this handle is enqueued on, or NULL: then the library's own
+ * stream for the current device (created on first device work, shared by all
+ * such handles, blocking, so ordered with work on the null stream).
+ * Allocates host metadata only.  Errors: EINVAL. */
 int hpmc_create(hpmc_sim** out, int64_t n, double box_L, uint64_t seed, uint32_t replica_id, int precision,
                 void* hip_stream);
 

@@ -163,10 +163,12 @@ class Sim:
         self.device = torch.device(device)
         self.n = int(n)
         self.L = float(box_L)
-        self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # no stream given: the library's own blocking stream (ordered with torch's
+        # null-stream work, and capturable into a graph)
+        self._stream = stream
         h = ctypes.c_void_p()
         rc = lib().hpmc_create(ctypes.byref(h), self.n, self.L, int(seed) & (2**64 - 1), int(replica_id),
-                               int(precision), ctypes.c_void_p(self._stream.cuda_stream))
+                               int(precision), ctypes.c_void_p(stream.cuda_stream if stream is not None else None))
         if rc != 0:
             raise HpmcError(rc, "hpmc_create")
         self._h = h
@@ -236,14 +238,14 @@ class Sim:
             q = torch.as_tensor(np.asarray(quat) if not torch.is_tensor(quat) else quat, dtype=torch.float64)
             self.quat = q.reshape(4, self.n).to(self.device).contiguous()
             qptr = ctypes.c_void_p(self.quat.data_ptr())
-        self._stream.synchronize()
+        torch.cuda.synchronize(self.device)  # the copies above ran on torch's stream
         self._chk(lib().hpmc_set_state(self._h, ctypes.c_void_p(self.pos.data_ptr()), qptr, int(sweep)), "set_state")
 
     def get_state(self):
         """(pos [3][n] numpy, quat [4][n] numpy or None, sweep index)."""
         sw = ctypes.c_uint64(0)
         self._chk(lib().hpmc_get_state(self._h, ctypes.byref(sw)), "get_state")
-        self._stream.synchronize()
+        self.torch.cuda.synchronize(self.device)  # sweeps still in flight on the handle's stream
         pos = self.pos.cpu().numpy().copy()
         quat = self.quat.cpu().numpy().copy() if self.quat is not None else None
         return pos, quat, int(sw.value)

@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -60,6 +61,10 @@ struct hpmc_sim {
     std::vector<hipEvent_t> events;  // timing of phase launches (counters requested)
     hipGraphExec_t graph = nullptr;  // one captured sweep, replayed for untimed multi-sweep calls
     std::vector<unsigned char> graph_key;
+    // side streams (default priority) that let the shape groups of a batched
+    // sweep run concurrently; created on first use
+    hipStream_t side[2] = {nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
     Desc desc{};                     // host copy of the device descriptor
     Desc* d_desc = nullptr;          // device descriptor (in the workspace)
     unsigned long long* d_gather = nullptr;
@@ -69,6 +74,11 @@ struct hpmc_sim {
     {
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
         if (graph) (void)hipGraphExecDestroy(graph);
+        for (int i = 0; i < 2; ++i) {
+            if (side[i]) (void)hipStreamDestroy(side[i]);
+            if (join[i]) (void)hipEventDestroy(join[i]);
+        }
+        if (fork) (void)hipEventDestroy(fork);
     }
 };
 
@@ -353,8 +363,23 @@ int set_sweep_dev(hpmc_sim* s)
     return e == hipSuccess ? HPMC_OK : hip_fail(s, e, "sweep counter");
 }
 
+// Handles created without a stream share one library stream per device: a
+// blocking stream, so it is ordered with work on the null stream, and a real
+// stream, so untimed multi-sweep calls can be captured into a graph.
+hipStream_t library_stream()
+{
+    static std::mutex mu;
+    static hipStream_t streams[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!streams[dev] && hipStreamCreate(&streams[dev]) != hipSuccess) streams[dev] = nullptr;
+    return streams[dev];
+}
+
 int check_ready(hpmc_sim* s, bool need_state)
 {
+    if (!s->stream) s->stream = library_stream();
     if (!s->have_shape) return fail(s, HPMC_ESTATE, "shape not set");
     if (!s->ws) return fail(s, HPMC_ESTATE, "workspace not set");
     if (s->ws_bytes < layout(s).total) return fail(s, HPMC_ENOMEM, "workspace too small for the current settings");
@@ -595,6 +620,32 @@ namespace {
 // Untimed sweeps of a fixed launch shape replay one captured sweep (a hipGraph
 // of its ~20 kernels): the kernels read descriptors and the sweep counter from
 // device memory, so the graph stays valid while the groups' shapes do.
+// one sweep of every group: group 0 on st, groups 1 and 2 (at most three
+// shape kinds) on the owner's side streams, forked from and joined back into st
+// by events, so small groups of different kinds overlap on the device
+hipError_t sweep_groups(hpmc_sim* owner, const std::vector<Group>& groups, hipStream_t st)
+{
+    if (groups.size() == 1) return launch_sweep(groups[0], nullptr, nullptr, st);
+    hipError_t e = hipSuccess;
+    if (!owner->fork) e = hipEventCreateWithFlags(&owner->fork, hipEventDisableTiming);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+        if (!owner->side[i]) e = hipStreamCreateWithFlags(&owner->side[i], hipStreamNonBlocking);
+        if (e == hipSuccess && !owner->join[i]) e = hipEventCreateWithFlags(&owner->join[i], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventRecord(owner->fork, st);
+    const size_t nside = std::min<size_t>(groups.size() - 1, 2);
+    for (size_t i = 0; i < nside && e == hipSuccess; ++i) {
+        e = hipStreamWaitEvent(owner->side[i], owner->fork, 0);
+        if (e == hipSuccess) e = launch_sweep(groups[i + 1], nullptr, nullptr, owner->side[i]);
+        if (e == hipSuccess) e = hipEventRecord(owner->join[i], owner->side[i]);
+    }
+    if (e == hipSuccess) e = launch_sweep(groups[0], nullptr, nullptr, st);
+    for (size_t i = nside + 1; i < groups.size() && e == hipSuccess; ++i)
+        e = launch_sweep(groups[i], nullptr, nullptr, st);
+    for (size_t i = 0; i < nside && e == hipSuccess; ++i) e = hipStreamWaitEvent(st, owner->join[i], 0);
+    return e;
+}
+
 hipError_t run_sweeps(hpmc_sim* owner, const std::vector<Group>& groups, int n, hipStream_t st)
 {
     std::vector<unsigned char> key(groups.size() * sizeof(Group));
@@ -608,8 +659,7 @@ hipError_t run_sweeps(hpmc_sim* owner, const std::vector<Group>& groups, int n, 
             }
             hipGraph_t graph = nullptr;
             e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
-            for (const Group& g : groups)
-                if (e == hipSuccess) e = launch_sweep(g, nullptr, nullptr, st);
+            if (e == hipSuccess) e = sweep_groups(owner, groups, st);
             hipError_t e2 = hipStreamEndCapture(st, &graph);
             if (e == hipSuccess) e = e2;
             if (e == hipSuccess) e = hipGraphInstantiate(&owner->graph, graph, nullptr, nullptr, 0);
@@ -623,9 +673,7 @@ hipError_t run_sweeps(hpmc_sim* owner, const std::vector<Group>& groups, int n, 
         for (int i = 0; i < n && e == hipSuccess; ++i) e = hipGraphLaunch(owner->graph, st);
         return e;
     }
-    for (int i = 0; i < n && e == hipSuccess; ++i)
-        for (const Group& g : groups)
-            if (e == hipSuccess) e = launch_sweep(g, nullptr, nullptr, st);
+    for (int i = 0; i < n && e == hipSuccess; ++i) e = sweep_groups(owner, groups, st);
     return e;
 }
 

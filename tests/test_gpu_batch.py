@@ -79,3 +79,30 @@ def test_batch_matches_oracle():
         po, _, _ = o.get_state()
         pg, _, _ = g.get_state()
         assert np.array_equal(po, pg), sp.name
+
+
+@pytest.mark.parametrize("counters", [True, False])
+def test_mixed_kinds_concurrent_groups(counters):
+    """Spheres, hemispheres and swept disks in one batch: the three shape
+    groups run on separate streams (and, for untimed multi-sweep calls, as
+    parallel branches of one graph); every replica still matches its lone run."""
+    import paper_1508_07077_amd as hp
+
+    sps = _replicas(wl.SPHERE, 3, 7) + _replicas(wl.DISCOID, 3, 8)
+    sps.append(wl.StatePoint(wl.HEMISPHERE, (1.0,), 150, 0.15, 0.15, 0.2, d_trans=0.04, a_rot=0.04, p_rot=0.5,
+                             seed=901, replica_id=99))
+    states = [sp.initial_state() for sp in sps]
+    batch = [_handle(sp, *st) for sp, st in zip(sps, states)]
+    alone = [_handle(sp, *st) for sp, st in zip(sps, states)]
+    b = hp.Batch(batch)
+    for _ in range(3):
+        b.sweep(2, counters=counters)
+    for a in alone:
+        a.sweep(6, counters=True)
+    for x, y in zip(batch, alone):
+        px, qx, sx = x.get_state()
+        py, qy, sy = y.get_state()
+        assert sx == sy == 6
+        assert np.array_equal(px, py)
+        if qx is not None:
+            assert np.array_equal(qx, qy)
