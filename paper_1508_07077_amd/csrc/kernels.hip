@@ -172,9 +172,10 @@ struct WaveCtx {
     int* list;          // stencil slots
     double4* own_pos;   // own-cell records (updated on accept)
     double4* own_q;
-    double* geo;        // per-trial geometry cache: D (3) [+ R (9)] per entry
+    double* geo;        // per-cell geometry cache: position (3) [+ R (9)] per entry
     int start, nc, nst;
     int jslot;
+    int jl;             // list index of the moved colloid (own members come first)
     Vec3 xn;
 };
 
@@ -211,7 +212,7 @@ __device__ inline void get_entry(const Params& P, const Work& W, const WaveCtx& 
 {
     if (i < P.geo_cap) {
         const double* g = c.geo + static_cast<size_t>(i) * Traits<KIND>::geo_stride;
-        D = v3(g[0], g[1], g[2]);
+        D = (i == c.jl) ? v3(kFar, kFar, kFar) : v3(mi(P, g[0] - c.xn.x), mi(P, g[1] - c.xn.y), mi(P, g[2] - c.xn.z));
         if constexpr (Traits<KIND>::oriented) {
 #pragma unroll
             for (int k = 0; k < 9; ++k) R.m[k] = g[3 + k];
@@ -610,6 +611,27 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
         for (int k = 0; k < ec; ++k) c.list[off + k] = es + k;
         c.nst = nst;
         wave_sync();
+        // geometry cache of the stencil, once per cell: positions and rotation
+        // matrices (the moved colloid's entry is updated when a move is accepted)
+        {
+            const int ng = c.nst < P.geo_cap ? c.nst : P.geo_cap;
+            for (int i = lane; i < ng; i += 64) {
+                int slot = c.list[i];
+                bool own = slot >= c.start && slot < c.start + c.nc;
+                double4 pp = own ? c.own_pos[slot - c.start] : W.rpos[slot];
+                double* g = c.geo + static_cast<size_t>(i) * GS;
+                g[0] = pp.x;
+                g[1] = pp.y;
+                g[2] = pp.z;
+                if constexpr (ORI) {
+                    double4 qq = own ? c.own_q[slot - c.start] : W.rquat[slot];
+                    Mat3 R = quat_to_mat(qq.x, qq.y, qq.z, qq.w);
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) g[3 + k] = R.m[k];
+                }
+            }
+            wave_sync();
+        }
 
         const int ntr = P.n_select * c.nc;
         for (int t = 0; t < ntr; ++t) {
@@ -633,6 +655,7 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
             const int jl = static_cast<int>(pick(sel0, static_cast<uint32_t>(c.nc)));
             const bool rotate = ORI && P.p_rot > 0.0 && u01(sel1) < P.p_rot;
             c.jslot = c.start + jl;
+            c.jl = jl;
             const double4 pj = c.own_pos[jl];
             double4 qj = make_double4(1.0, 0.0, 0.0, 0.0);
             if constexpr (ORI) qj = c.own_q[jl];
@@ -697,29 +720,15 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
             if (cell_of(P, xn.x, xn.y, xn.z, g0, g1, g2) != C) {
                 o.reason = 1;
             } else {
-                // --- geometry cache of the stencil relative to x' ----------------
-                // (lane i also keeps entry i in registers for the survivor tests)
-                const int ng = c.nst < P.geo_cap ? c.nst : P.geo_cap;
+                // stencil entries beyond the cache: lane i keeps entry i in registers
+                // (survivor tests of the unoriented instantiation)
                 Vec3 Dreg = v3(kFar, kFar, kFar);
-                if (lane < c.nst && lane >= ng) {
-                    Mat3 R;
-                    load_entry<KIND>(P, W, c, lane, Dreg, R);
-                }
-                for (int i = lane; i < ng; i += 64) {
-                    Vec3 D;
-                    Mat3 R;
-                    load_entry<KIND>(P, W, c, i, D, R);
-                    if (i == lane) Dreg = D;
-                    double* g = c.geo + static_cast<size_t>(i) * GS;
-                    g[0] = D.x;
-                    g[1] = D.y;
-                    g[2] = D.z;
-                    if constexpr (ORI) {
-#pragma unroll
-                        for (int k = 0; k < 9; ++k) g[3 + k] = R.m[k];
+                if constexpr (!ORI) {
+                    if (lane < c.nst) {
+                        Mat3 R;
+                        get_entry<KIND>(P, W, c, lane, Dreg, R);
                     }
                 }
-                wave_sync();
                 Mat3 Rn, Ro;
                 if constexpr (ORI) {
                     Rn = quat_to_mat(qn[0], qn[1], qn[2], qn[3]);
@@ -850,6 +859,17 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
             if (o.reason == 0 && lane == 0) {
                 c.own_pos[jl] = make_double4(xn.x, xn.y, xn.z, pj.w);
                 if constexpr (ORI) c.own_q[jl] = make_double4(qn[0], qn[1], qn[2], qn[3]);
+                if (jl < P.geo_cap) {
+                    double* g = c.geo + static_cast<size_t>(jl) * GS;
+                    g[0] = xn.x;
+                    g[1] = xn.y;
+                    g[2] = xn.z;
+                    if constexpr (ORI) {
+                        Mat3 R = quat_to_mat(qn[0], qn[1], qn[2], qn[3]);
+#pragma unroll
+                        for (int k = 0; k < 9; ++k) g[3 + k] = R.m[k];
+                    }
+                }
             }
             wave_sync();
             cnt[cTrials] += 1;
