@@ -311,6 +311,7 @@ Group make_group(const Desc* d, const hpmc_sim* const* sims, int n)
     g.nrep = n;
     g.kind = sims[0]->S.kind;
     g.precision = sims[0]->precision;
+    g.shell = sims[0]->region == HPMC_V0_SHELL;
     g.wpb = 4;
     g.chunk = sims[0]->tune_chunk ? sims[0]->tune_chunk : kChunk;
     g.max_waves = sims[0]->tune_waves ? sims[0]->tune_waves : kMaxWaves;
@@ -872,13 +873,13 @@ int hpmc_sweep_batch(hpmc_sim* const* sims, int n_sims, void* batch_ws, size_t b
         if (sims[i]->trace) return fail(sims[i], HPMC_EINVAL, "tracing is per handle; disable it for batched sweeps");
     }
     hipStream_t st = sims[0]->stream;
-    // replicas that share a shape kind and precision share each launch; groups run one after another
+    // replicas that share a shape kind, precision and insertion region share each launch
     Desc* d_all = static_cast<Desc*>(batch_ws);
     unsigned long long* d_gather = reinterpret_cast<unsigned long long*>(
         static_cast<unsigned char*>(batch_ws) + align256(static_cast<size_t>(n_sims) * sizeof(Desc)));
     std::vector<int> order;
-    auto cls = [&](int i) { return 2 * sims[i]->S.kind + sims[i]->precision; };
-    for (int k = 0; k < 6; ++k)
+    auto cls = [&](int i) { return 4 * sims[i]->S.kind + 2 * sims[i]->precision + sims[i]->region; };
+    for (int k = 0; k < 12; ++k)
         for (int i = 0; i < n_sims; ++i)
             if (cls(i) == k) order.push_back(i);
     std::vector<Desc> host(static_cast<size_t>(n_sims));

@@ -138,10 +138,11 @@ __device__ inline Words draw(const Params& P, uint32_t cell, uint32_t t, uint32_
 // 4-ball candidate: 25-bit fields, odd m in (-2^25, 2^25), accepted iff sum m^2 < 2^50
 // depletant candidates of block `blk` of a trial's insertion stream: two ball
 // candidates (V_0 = B(x', R0)) or one shell candidate (V_0 = the shell)
-__device__ inline void depl_candidates(const Params& P, uint32_t cell, uint32_t t, uint32_t blk, bool& acc0, bool& acc1,
-                                       Vec3& e0, Vec3& e1)
+template <bool SHELL>
+__device__ inline void depl_candidates_t(const Params& P, uint32_t cell, uint32_t t, uint32_t blk, bool& acc0,
+                                         bool& acc1, Vec3& e0, Vec3& e1)
 {
-    if (P.shell) {
+    if constexpr (SHELL) {
         Words dw = draw(P, cell, t, kDeplShell, blk);
         double x, y, z;
         acc0 = shell3(dw, P.r_inner, P.span, P.S.R0sq, x, y, z);
@@ -156,6 +157,15 @@ __device__ inline void depl_candidates(const Params& P, uint32_t cell, uint32_t 
         e0 = v3(P.s_ball * a0, P.s_ball * a1, P.s_ball * a2);
         e1 = v3(P.s_ball * b0, P.s_ball * b1, P.s_ball * b2);
     }
+}
+
+__device__ inline void depl_candidates(const Params& P, uint32_t cell, uint32_t t, uint32_t blk, bool& acc0, bool& acc1,
+                                       Vec3& e0, Vec3& e1)
+{
+    if (P.shell)
+        depl_candidates_t<true>(P, cell, t, blk, acc0, acc1, e0, e1);
+    else
+        depl_candidates_t<false>(P, cell, t, blk, acc0, acc1, e0, e1);
 }
 
 __device__ inline bool ball4(Words w, double m[4])
@@ -1007,7 +1017,7 @@ __device__ inline bool sphere_hit_lane(const Params& P, const Work& W, const Sph
     return hit && active;
 }
 
-template <bool F32>
+template <bool F32, bool SHELL>
 __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W, int phase)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1169,7 +1179,7 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
                         while (!done && kbase < Np && blk < (1u << 30)) {
                             bool acc0, acc1;
                             Vec3 e0, e1;
-                            depl_candidates(P, static_cast<uint32_t>(C), static_cast<uint32_t>(t), blk + lane, acc0,
+                            depl_candidates_t<SHELL>(P, static_cast<uint32_t>(C), static_cast<uint32_t>(t), blk + lane, acc0,
                                             acc1, e0, e1);
                             unsigned long long m0 = __ballot(acc0), m1 = __ballot(acc1);
                             uint32_t k0 = kbase + static_cast<uint32_t>(bits_below(m0) + bits_below(m1));
@@ -1318,15 +1328,16 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
 #ifndef HPMC_SPHERE_WAVES_PER_EU
 #define HPMC_SPHERE_WAVES_PER_EU 3
 #endif
-// F32: depletant tests in FP32 with the FP64 guard band (precision HPMC_FP32_GUARDED)
-template <bool F32>
+// F32: depletant tests in FP32 with the FP64 guard band (precision HPMC_FP32_GUARDED);
+// SHELL: depletants in the shell region
+template <bool F32, bool SHELL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F32 ? 2 : HPMC_SPHERE_WAVES_PER_EU, 8))) void
 phase_sphere_kernel(const Desc* __restrict__ D, int phase)
 {
     Params P = D[blockIdx.y].P;
     const Work W = D[blockIdx.y].W;
     P.sweep = *W.sweep_dev;
-    phase_sphere_body<F32>(P, W, phase);
+    phase_sphere_body<F32, SHELL>(P, W, phase);
 }
 
 template <int KIND>
@@ -1488,8 +1499,8 @@ __global__ __launch_bounds__(256) void free_volume_kernel(const Desc* __restrict
     if (lane_id() == 0 && tot) atomicAdd(&W.obs[slot], static_cast<unsigned long long>(tot));
 }
 
-// per-particle smallest compression of a neighbour separation at which the
-// pair overlaps (scale-distribution function); histogram in W.obs
+// Scale-distribution function (per-particle smallest compression at which a
+// neighbour pair overlaps, histogram in W.obs).
 // Scale factor at which the pair (A at the origin, B at offset d) first
 // overlaps when the centre distance is compressed by (1 - x): bisection of
 // [0, x_max] in 40 steps (overlap grows monotonically with x).
@@ -1640,12 +1651,15 @@ hipError_t launch_phase(const Group& g, int phase, hipStream_t stream)
     dim3 bs(64 * g.wpb);
     if (g.kind == kSphere) {
         int waves = blocks_for(g.maxActive, g.chunk);
-        if (g.precision == 1)
-            hipLaunchKernelGGL(phase_sphere_kernel<true>, dim3(blocks_for(waves, g.wpb), R), bs, g.lds, stream, g.d,
-                               phase);
+        dim3 grid(blocks_for(waves, g.wpb), R);
+        if (g.precision == 1 && g.shell)
+            hipLaunchKernelGGL((phase_sphere_kernel<true, true>), grid, bs, g.lds, stream, g.d, phase);
+        else if (g.precision == 1)
+            hipLaunchKernelGGL((phase_sphere_kernel<true, false>), grid, bs, g.lds, stream, g.d, phase);
+        else if (g.shell)
+            hipLaunchKernelGGL((phase_sphere_kernel<false, true>), grid, bs, g.lds, stream, g.d, phase);
         else
-            hipLaunchKernelGGL(phase_sphere_kernel<false>, dim3(blocks_for(waves, g.wpb), R), bs, g.lds, stream, g.d,
-                               phase);
+            hipLaunchKernelGGL((phase_sphere_kernel<false, false>), grid, bs, g.lds, stream, g.d, phase);
     } else {
         int waves = g.maxActive < g.max_waves ? g.maxActive : g.max_waves;
         if (R > 1 && waves > 512) waves = 512;
