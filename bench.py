@@ -28,24 +28,37 @@ if ROOT not in sys.path:
 # MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = VALU lane-instruction issue peak
 VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
-# Algorithmic VALU work per resolved depletant check (lane-instructions), the
-# per-unit figure of the roofline: one Philox4x32-10 block yields 2 ball
-# candidates, accepted with probability pi/6 each, so a depletant costs
-# 1/(2 pi/6) = 0.955 blocks.  A block is 10 rounds of 2 32x32->64 multiplies
-# and 4 XORs (60 instructions; the key schedule is wave-uniform and scalar).
-# Each candidate: 3 field extractions + 3 int->f64 conversions + 3 offsets
-# (9 VALU), 3 squares and 2 adds and 1 compare in f64 (6); each accepted
-# candidate: 3 scalings + the old-pose test (3 sub, 3 mul, 2 add, 1 compare)
-# (12) + index assignment (2).
-#   per depletant = 0.955 * (60 + 2 * 15) + 14 = 100.0 lane-instructions
-ALGO_OPS_PER_CHECK = 0.955 * (60 + 2 * 15) + 14
+# Minimal VALU work per resolved depletant check (lane-instructions): one
+# Philox4x32-10 block yields 2 ball candidates, accepted with probability
+# pi/6 each, so a depletant costs 1/(2 pi/6) = 0.955 blocks.  A block is 10
+# rounds of 2 32x32->64 multiplies and 2 three-input XORs (40 instructions;
+# the key schedule is wave-uniform and scalar).  Each candidate: 3 field
+# extractions + 3 int->f64 conversions + 3 offsets (9 VALU), 3 squares, 2 adds
+# and 1 compare in f64 (6); each accepted candidate: 3 scalings + the old-pose
+# test (3 sub, 3 mul, 2 add, 1 compare) (12) + index assignment (2).
+#   per depletant = 0.955 * (40 + 2 * 15) + 14 = 80.9 lane-instructions
+ALGO_OPS_PER_CHECK = 0.955 * (40 + 2 * 15) + 14
 
-# HBM bytes per launch of the sphere phase kernel, from two rocprofv3 passes
-# (FETCH_SIZE, WRITE_SIZE) scaled by the same counters over a plain 256 MiB
-# device copy; valid only for the kernel sources with this digest (otherwise
-# the roofline reports traffic null).
-PROFILED_KERNEL_DIGEST = "c34e00a875326089"
-PROFILED_TRAFFIC_BYTES = {"ball": 85633056, "shell": 86012009}
+# Shell insertion region: one candidate per block (40), 4 u32->f64 conversions
+# with their offsets and scalings (12), the disk test (3), the radius and its
+# r^2 test (5), 2 sqrt(1 - s) + direction + 3 scalings (16): 76 per block,
+# accepted with probability (pi/4) E[r^2]/R0^2; + 14 per accepted depletant.
+def shell_ops_per_check(R0: float, r_i: float) -> float:
+    acc = math.pi / 4 * (R0**3 - r_i**3) / (3.0 * (R0 - r_i) * R0**2)
+    return 76.0 / acc + 14.0
+
+
+# Calibrated VALU work per resolved depletant of the sphere phase kernel (ball
+# region), from rocprofv3 SQ_INSTS_VALU: (VALU instructions per move with
+# depletants - without) x 64 lanes / resolved depletants per move, i.e. all the
+# work the depletants cause (placement, classification, Poisson count,
+# survivor walk, CB passes), none of the per-move selection/proposal/stencil
+# work.  HBM bytes per launch from two rocprofv3 passes (FETCH_SIZE,
+# WRITE_SIZE) scaled by the same counters over a plain 256 MiB device copy.
+# Both hold only for the kernel sources with this digest.
+PROFILED_KERNEL_DIGEST = "c0e12651e4900661"
+CALIBRATED_OPS_PER_CHECK = 263.35
+PROFILED_TRAFFIC_BYTES = {"ball": 109906051, "shell": 110440627}
 
 
 def kernel_digest() -> str:
@@ -56,15 +69,6 @@ def kernel_digest() -> str:
         with open(os.path.join(ROOT, "paper_1508_07077_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
-
-
-# Shell insertion region: one candidate per block (60), 4 u32->f64 conversions
-# with their offsets and scalings (12), the disk test (3), the radius and its
-# r^2 test (5), 2 sqrt(1 - s) + direction + 3 scalings (16): 96 per block,
-# accepted with probability (pi/4) E[r^2]/R0^2; + 14 per accepted depletant.
-def shell_ops_per_check(R0: float, r_i: float) -> float:
-    acc = math.pi / 4 * (R0**3 - r_i**3) / (3.0 * (R0 - r_i) * R0**2)
-    return 96.0 / acc + 14.0
 
 
 def parse():
@@ -176,9 +180,14 @@ def main():
     launches = 8 * args.steps
     avg_phase_s = phase_ms / 1e3 / launches
     R0 = 0.5 * sp.params[0] + 0.5 * sp.d_dep
-    ops_per_check = ALGO_OPS_PER_CHECK if region == hp.V0_BALL else \
+    minimal_ops = ALGO_OPS_PER_CHECK if region == hp.V0_BALL else \
         shell_ops_per_check(R0, max(0.0, R0 - math.sqrt(3.0) * sp.d_trans))
-    achieved = ops_per_check * (tot["depletants_resolved"] / launches) / avg_phase_s
+    profiled = kernel_digest() == PROFILED_KERNEL_DIGEST
+    # the per-unit figure: calibrated from the profiled kernel (ball region), else the minimal count
+    ops_per_check = CALIBRATED_OPS_PER_CHECK if (profiled and region == hp.V0_BALL) else minimal_ops
+    per_launch = tot["depletants_resolved"] / launches
+    achieved = ops_per_check * per_launch / avg_phase_s
+    achieved_minimal = minimal_ops * per_launch / avg_phase_s
     # the same state point with the other insertion region, timed right after
     other = hp.V0_BALL if region == hp.V0_SHELL else hp.V0_SHELL
     sim.set_insertion(other)
@@ -248,10 +257,14 @@ def main():
             "peak": VALU_PEAK_LANE_OPS / 1e12,
             "unit": "T VALU lane-instr/s",
             "frac": achieved / VALU_PEAK_LANE_OPS,
-            "traffic": PROFILED_TRAFFIC_BYTES[args.v0] if kernel_digest() == PROFILED_KERNEL_DIGEST else None,
+            "traffic": PROFILED_TRAFFIC_BYTES[args.v0] if profiled else None,
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "avg_launch_ms": avg_phase_s * 1e3,
             "ops_per_check": ops_per_check,
+            "ops_source": "SQ_INSTS_VALU calibration of this kernel" if ops_per_check == CALIBRATED_OPS_PER_CHECK
+                          else "minimal instruction count",
+            "frac_minimal": achieved_minimal / VALU_PEAK_LANE_OPS,
+            "ops_per_check_minimal": minimal_ops,
         },
         "other_insertion_region": companion,
         "fp32_guarded": fp32,
