@@ -325,6 +325,10 @@ Group make_group(const Desc* d, const hpmc_sim* const* sims, int n)
         wave_lds = std::max(wave_lds, static_cast<size_t>(P.wave_lds));
     }
     g.lds = kTableLds + static_cast<size_t>(g.wpb) * wave_lds;
+    // small sphere boxes sweep in one workgroup per replica, many sweeps per launch
+    g.lds_small = kTableLds + static_cast<size_t>(kSmallWaves) * wave_lds;
+    g.small = g.kind == kSphere && g.maxActive <= kSmallMaxActive && g.maxN <= kSmallMaxN &&
+              g.lds_small <= 64 * 1024;
     return g;
 }
 
@@ -649,6 +653,15 @@ hipError_t sweep_groups(hpmc_sim* owner, const std::vector<Group>& groups, hipSt
 
 hipError_t run_sweeps(hpmc_sim* owner, const std::vector<Group>& groups, int n, hipStream_t st)
 {
+    bool all_small = !groups.empty();
+    for (const Group& g : groups) all_small = all_small && g.small;
+    if (all_small) {
+        // every group sweeps in one launch of n sweeps: no graph needed
+        hipError_t e = hipSuccess;
+        for (const Group& g : groups)
+            if (e == hipSuccess && n > 0) e = launch_sweep_small(g, n, st);
+        return e;
+    }
     std::vector<unsigned char> key(groups.size() * sizeof(Group));
     if (!groups.empty()) memcpy(key.data(), groups.data(), key.size());
     hipError_t e = hipSuccess;

@@ -1017,16 +1017,23 @@ __device__ inline bool sphere_hit_lane(const Params& P, const Work& W, const Sph
     return hit && active;
 }
 
-template <bool F32, bool SHELL>
-__device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W, int phase)
+// Poisson table and its guide into the workgroup's LDS (before any phase body)
+__device__ inline void load_table(const Work& W, unsigned char* smem)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
     double* sF = reinterpret_cast<double*>(smem);
     int* sG = reinterpret_cast<int*>(smem + kPoissonK * sizeof(double));
     const int* gG = reinterpret_cast<const int*>(W.F + kPoissonK);
     for (int i = threadIdx.x; i < kPoissonK; i += blockDim.x) sF[i] = W.F[i];
     for (int i = threadIdx.x; i < kGuide; i += blockDim.x) sG[i] = gG[i];
-    __syncthreads();
+}
+
+// One wave's share of a phase: the chunk gw of active cells (P.chunk cells).
+template <bool F32, bool SHELL>
+__device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W, int phase, int gw)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    double* sF = reinterpret_cast<double*>(smem);
+    int* sG = reinterpret_cast<int*>(smem + kPoissonK * sizeof(double));
 
     const int lane = lane_id();
     const int wv = threadIdx.x >> 6;
@@ -1042,7 +1049,6 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
     for (int k = 0; k < kNumCounters; ++k) cnt[k] = 0ull;
 
     const int colour = W.perm[phase];
-    const int gw = blockIdx.x * P.waves_per_block + wv;
     const double g0 = W.grid[0], g1 = W.grid[1], g2 = W.grid[2];
     const Mat3 Rnone{};
 
@@ -1337,7 +1343,119 @@ phase_sphere_kernel(const Desc* __restrict__ D, int phase)
     Params P = D[blockIdx.y].P;
     const Work W = D[blockIdx.y].W;
     P.sweep = *W.sweep_dev;
-    phase_sphere_body<F32, SHELL>(P, W, phase);
+    extern __shared__ __align__(16) unsigned char smem[];
+    load_table(W, smem);
+    __syncthreads();
+    phase_sphere_body<F32, SHELL>(P, W, phase, static_cast<int>(blockIdx.x) * P.waves_per_block +
+                                                   static_cast<int>(threadIdx.x >> 6));
+}
+
+// Small sphere boxes: one workgroup of kSmallWaves waves sweeps a whole
+// replica, n_sweeps sweeps in one launch (grid shift and colour order, cell
+// list, the 8 phases, scatter back), with workgroup barriers between the
+// steps instead of kernel boundaries.  The same arithmetic as the multi-kernel
+// sweep, so the same trajectory.
+__device__ inline void grid_setup(const Params& P, const Work& W)
+{
+    Words a = draw(P, kNoCell, 0, kGrid, 0);
+    W.grid[0] = P.w * u01(a.w0);
+    W.grid[1] = P.w * u01(a.w1);
+    W.grid[2] = P.w * u01(a.w2);
+    Words b = draw(P, kNoCell, 0, kGrid, 1);
+    Words c = draw(P, kNoCell, 0, kGrid, 2);
+    uint32_t fy[7] = {b.w0, b.w1, b.w2, b.w3, c.w0, c.w1, c.w2};
+    int perm[8] = {0, 1, 2, 3, 4, 5, 6, 7};
+    for (int i = 7, f = 0; i >= 1; --i, ++f) {
+        int j = static_cast<int>(pick(fy[f], static_cast<uint32_t>(i + 1)));
+        int tmp = perm[i];
+        perm[i] = perm[j];
+        perm[j] = tmp;
+    }
+    for (int i = 0; i < 8; ++i) W.perm[i] = perm[i];
+}
+
+template <bool F32, bool SHELL>
+__global__ __launch_bounds__(64 * kSmallWaves) void sweep_small_kernel(const Desc* __restrict__ D, int n_sweeps)
+{
+    Params P = D[blockIdx.y].P;
+    const Work W = D[blockIdx.y].W;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_wsum[kSmallWaves];
+    __shared__ int s_carry;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int wv = tid >> 6;
+    const uint32_t sweep0 = *W.sweep_dev;
+    // spread the active cells of a phase over the waves (trials of one cell are serial)
+    P.chunk = (P.active_cells + kSmallWaves - 1) / kSmallWaves;
+    if (P.chunk > 64) P.chunk = 64;
+    load_table(W, smem);
+    for (int sw = 0; sw < n_sweeps; ++sw) {
+        P.sweep = sweep0 + static_cast<uint32_t>(sw);
+        if (tid == 0) grid_setup(P, W);
+        for (int i = tid; i < P.ncells; i += nt) W.cell_count[i] = 0;
+        __syncthreads();
+        for (int i = tid; i < P.N; i += nt) {
+            int c = cell_of(P, W.pos[i], W.pos[P.N + i], W.pos[2 * P.N + i], W.grid[0], W.grid[1], W.grid[2]);
+            W.pcell[i] = c;
+            W.prank[i] = atomicAdd(&W.cell_count[c], 1);
+        }
+        if (tid == 0) s_carry = 0;
+        __syncthreads();
+        // exclusive scan of the cell counts, one thread per cell, tile by tile
+        for (int base = 0; base < P.ncells; base += nt) {
+            int i = base + tid;
+            int v = i < P.ncells ? W.cell_count[i] : 0;
+            int tot;
+            int ex = wave_excl_scan(v, tot);
+            if (lane_id() == 0) s_wsum[wv] = tot;
+            __syncthreads();
+            int woff = 0, all = 0;
+            for (int k = 0; k < kSmallWaves; ++k) {
+                if (k < wv) woff += s_wsum[k];
+                all += s_wsum[k];
+            }
+            if (i < P.ncells) W.cell_start[i] = s_carry + woff + ex;
+            __syncthreads();
+            if (tid == 0) s_carry += all;
+            __syncthreads();
+        }
+        if (tid == 0) W.cell_start[P.ncells] = P.N;
+        __syncthreads();
+        for (int i = tid; i < P.N; i += nt) W.order[W.cell_start[W.pcell[i]] + W.prank[i]] = i;
+        __syncthreads();
+        for (int c = tid; c < P.ncells; c += nt) {
+            int s0 = W.cell_start[c], e = W.cell_start[c + 1];
+            for (int i = s0 + 1; i < e; ++i) {
+                int v = W.order[i];
+                int j = i - 1;
+                while (j >= s0 && W.order[j] > v) {
+                    W.order[j + 1] = W.order[j];
+                    --j;
+                }
+                W.order[j + 1] = v;
+            }
+        }
+        __syncthreads();
+        for (int q = tid; q < P.N; q += nt) {
+            int i = W.order[q];
+            W.rpos[q] = make_double4(W.pos[i], W.pos[P.N + i], W.pos[2 * P.N + i], static_cast<double>(i));
+        }
+        __syncthreads();
+        for (int phase = 0; phase < 8; ++phase) {
+            for (int gw = wv; gw * P.chunk < P.active_cells; gw += kSmallWaves)
+                phase_sphere_body<F32, SHELL>(P, W, phase, gw);
+            __syncthreads();
+        }
+        for (int q = tid; q < P.N; q += nt) {
+            double4 r = W.rpos[q];
+            int i = static_cast<int>(r.w);
+            W.pos[i] = r.x;
+            W.pos[P.N + i] = r.y;
+            W.pos[2 * P.N + i] = r.z;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) *W.sweep_dev = sweep0 + static_cast<uint32_t>(n_sweeps);
 }
 
 template <int KIND>
@@ -1672,8 +1790,28 @@ hipError_t launch_phase(const Group& g, int phase, hipStream_t stream)
     return hipGetLastError();
 }
 
+hipError_t launch_sweep_small(const Group& g, int n_sweeps, hipStream_t stream)
+{
+    dim3 grid(1, g.nrep), bs(64 * kSmallWaves);
+    if (g.precision == 1 && g.shell)
+        hipLaunchKernelGGL((sweep_small_kernel<true, true>), grid, bs, g.lds_small, stream, g.d, n_sweeps);
+    else if (g.precision == 1)
+        hipLaunchKernelGGL((sweep_small_kernel<true, false>), grid, bs, g.lds_small, stream, g.d, n_sweeps);
+    else if (g.shell)
+        hipLaunchKernelGGL((sweep_small_kernel<false, true>), grid, bs, g.lds_small, stream, g.d, n_sweeps);
+    else
+        hipLaunchKernelGGL((sweep_small_kernel<false, false>), grid, bs, g.lds_small, stream, g.d, n_sweeps);
+    return hipGetLastError();
+}
+
 hipError_t launch_sweep(const Group& g, hipEvent_t phases_begin, hipEvent_t phases_end, hipStream_t stream)
 {
+    if (g.small) {
+        hipError_t e = phases_begin ? hipEventRecord(phases_begin, stream) : hipSuccess;
+        if (e == hipSuccess) e = launch_sweep_small(g, 1, stream);
+        if (e == hipSuccess && phases_end) e = hipEventRecord(phases_end, stream);
+        return e;
+    }
     hipError_t e = launch_build_cells(g, true, stream);
     if (e == hipSuccess && phases_begin) e = hipEventRecord(phases_begin, stream);
     for (int p = 0; p < 8 && e == hipSuccess; ++p) e = launch_phase(g, p, stream);

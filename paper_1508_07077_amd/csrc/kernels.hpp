@@ -104,6 +104,8 @@ struct Group {
     int chunk;      // spheres: active cells per wave (common to the group)
     int max_waves;  // oriented shapes: waves of the grid-stride phase launch
     size_t lds;     // dynamic LDS bytes of the phase kernel (common to the group)
+    int small;      // spheres in small boxes: one workgroup sweeps each replica (sweep_small_kernel)
+    size_t lds_small;
 };
 
 // host-side launchers (enqueue on `stream`)
@@ -112,6 +114,7 @@ hipError_t launch_fill_u64(unsigned long long* p, int n, hipStream_t stream);
 hipError_t launch_build_cells(const Group& g, bool with_grid, hipStream_t stream);
 hipError_t launch_phase(const Group& g, int phase, hipStream_t stream);
 hipError_t launch_sweep(const Group& g, hipEvent_t phases_begin, hipEvent_t phases_end, hipStream_t stream);
+hipError_t launch_sweep_small(const Group& g, int n_sweeps, hipStream_t stream);
 hipError_t launch_clear_counters(const Group& g, hipStream_t stream);
 hipError_t launch_overlap_count(const Group& g, hipStream_t stream);
 hipError_t launch_reduce_counters(const Group& g, unsigned long long* gather_out, hipStream_t stream);
@@ -122,5 +125,8 @@ hipError_t launch_sdf(const Group& g, const Params& P, const Work& W, int n_bins
 
 constexpr int kChunk = 16;  // default active cells per wave of the sphere phase kernel
 constexpr int kMaxWaves = 256 * 32;  // default wave count of the oriented phase launch
+constexpr int kSmallMaxActive = 256; // spheres with at most this many active cells per phase and
+constexpr int kSmallMaxN = 8192;     // at most this many particles sweep in one workgroup
+constexpr int kSmallWaves = 8;       // waves of that workgroup
 
 }  // namespace hpmc
