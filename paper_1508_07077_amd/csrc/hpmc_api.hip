@@ -63,8 +63,8 @@ struct hpmc_sim {
     std::vector<unsigned char> graph_key;
     // side streams (default priority) that let the shape groups of a batched
     // sweep run concurrently; created on first use
-    hipStream_t side[2] = {nullptr, nullptr};
-    hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
+    hipStream_t side[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
     Desc desc{};                     // host copy of the device descriptor
     Desc* d_desc = nullptr;          // device descriptor (in the workspace)
     unsigned long long* d_gather = nullptr;
@@ -74,7 +74,7 @@ struct hpmc_sim {
     {
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
         if (graph) (void)hipGraphExecDestroy(graph);
-        for (int i = 0; i < 2; ++i) {
+        for (int i = 0; i < 3; ++i) {
             if (side[i]) (void)hipStreamDestroy(side[i]);
             if (join[i]) (void)hipEventDestroy(join[i]);
         }
@@ -625,20 +625,20 @@ namespace {
 // Untimed sweeps of a fixed launch shape replay one captured sweep (a hipGraph
 // of its ~20 kernels): the kernels read descriptors and the sweep counter from
 // device memory, so the graph stays valid while the groups' shapes do.
-// one sweep of every group: group 0 on st, groups 1 and 2 (at most three
-// shape kinds) on the owner's side streams, forked from and joined back into st
-// by events, so small groups of different kinds overlap on the device
+// one sweep of every group: group 0 on st, groups 1 to 3 on the owner's side
+// streams (forked from and joined back into st by events), any further group
+// on st, so groups of different kinds and sizes overlap on the device
 hipError_t sweep_groups(hpmc_sim* owner, const std::vector<Group>& groups, hipStream_t st)
 {
     if (groups.size() == 1) return launch_sweep(groups[0], nullptr, nullptr, st);
     hipError_t e = hipSuccess;
     if (!owner->fork) e = hipEventCreateWithFlags(&owner->fork, hipEventDisableTiming);
-    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+    for (int i = 0; i < 3 && e == hipSuccess; ++i) {
         if (!owner->side[i]) e = hipStreamCreateWithFlags(&owner->side[i], hipStreamNonBlocking);
         if (e == hipSuccess && !owner->join[i]) e = hipEventCreateWithFlags(&owner->join[i], hipEventDisableTiming);
     }
     if (e == hipSuccess) e = hipEventRecord(owner->fork, st);
-    const size_t nside = std::min<size_t>(groups.size() - 1, 2);
+    const size_t nside = std::min<size_t>(groups.size() - 1, 3);
     for (size_t i = 0; i < nside && e == hipSuccess; ++i) {
         e = hipStreamWaitEvent(owner->side[i], owner->fork, 0);
         if (e == hipSuccess) e = launch_sweep(groups[i + 1], nullptr, nullptr, owner->side[i]);
@@ -891,8 +891,20 @@ int hpmc_sweep_batch(hpmc_sim* const* sims, int n_sims, void* batch_ws, size_t b
     unsigned long long* d_gather = reinterpret_cast<unsigned long long*>(
         static_cast<unsigned char*>(batch_ws) + align256(static_cast<size_t>(n_sims) * sizeof(Desc)));
     std::vector<int> order;
-    auto cls = [&](int i) { return 4 * sims[i]->S.kind + 2 * sims[i]->precision + sims[i]->region; };
-    for (int k = 0; k < 12; ++k)
+    // small sphere boxes form their own groups (one workgroup sweeps each)
+    auto small_ok = [&](int i) {
+        if (sims[i]->S.kind != HPMC_SPHERE) return 0;
+        Params Pi = make_params(sims[i]);
+        return (Pi.active_cells <= kSmallMaxActive && Pi.N <= kSmallMaxN &&
+                kTableLds + static_cast<size_t>(kSmallWaves) * Pi.wave_lds <= 64 * 1024)
+                   ? 1
+                   : 0;
+    };
+    std::vector<int> cl(static_cast<size_t>(n_sims));
+    for (int i = 0; i < n_sims; ++i)
+        cl[static_cast<size_t>(i)] = 8 * sims[i]->S.kind + 4 * small_ok(i) + 2 * sims[i]->precision + sims[i]->region;
+    auto cls = [&](int i) { return cl[static_cast<size_t>(i)]; };
+    for (int k = 0; k < 24; ++k)
         for (int i = 0; i < n_sims; ++i)
             if (cls(i) == k) order.push_back(i);
     std::vector<Desc> host(static_cast<size_t>(n_sims));

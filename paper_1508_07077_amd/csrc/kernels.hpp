@@ -125,7 +125,7 @@ hipError_t launch_sdf(const Group& g, const Params& P, const Work& W, int n_bins
 
 constexpr int kChunk = 16;  // default active cells per wave of the sphere phase kernel
 constexpr int kMaxWaves = 256 * 32;  // default wave count of the oriented phase launch
-constexpr int kSmallMaxActive = 256; // spheres with at most this many active cells per phase and
+constexpr int kSmallMaxActive = 32;  // spheres with at most this many active cells per phase and
 constexpr int kSmallMaxN = 8192;     // at most this many particles sweep in one workgroup
 constexpr int kSmallWaves = 8;       // waves of that workgroup
 
