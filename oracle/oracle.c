@@ -12,7 +12,8 @@
  * The steps below follow the paper in its order and notation:
  *   Sec. III.A  ensemble weight exp(z_p V_f - beta H_cc)           (Eq. gc_ensemble)
  *   Sec. III.B  move, Poisson depletant number, reject on overlap  (Eqs. move_gen, pacc; Fig. 2)
- *   Sec. III.C  V_0 = circumsphere around the new pose             (Eq. transition_prob_final)
+ *   Sec. III.C  V_0 = circumsphere around the new pose, or that   (Eq. transition_prob_final)
+ *               ball less a core ball inside the old pose (shell)
  *   Sec. III.D  configurational-bias re-insertion                  (Eq. pacc_cb; Fig. 3)
  *   Sec. III.E  checkerboard: inactive layer of width d_c + d_dep,
  *               particles may not leave their cell, random colour
@@ -26,6 +27,8 @@
  *   depletant/shape predicates                            pinned (dense point clouds)
  *   convex pair test (GJK)                                pinned (brute force on random pairs)
  *   trial move, CB weights, sweep                         pinned (closed forms P1/P2/P3/P6, explicit depletants)
+ *   shell insertion region and its sampler                pinned (radial CDF, isotropy, closed forms,
+ *                                                         forward/backward ratio, ball/shell invariance)
  *   g(r), free volume                                     pinned (brute force / analytic limits)
  *   SDF pressure                                          pinned only in its limits (z_p = 0 spheres vs
  *                                                         Carnahan-Starling, dilute limit); otherwise
