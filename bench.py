@@ -377,6 +377,7 @@ def bench_c2(args):
     per = {}
     moves = checks = secs = 0.0
     lat = []
+    fp32 = {}
     for eta in (0.1, 0.2, 0.3, 0.4):
         sp = wl.c2_hemispheres(eta)
         sim = _make(hp, sp)
@@ -399,9 +400,23 @@ def bench_c2(args):
         moves += tot["trials"]
         checks += tot["depletants_resolved"]
         secs += dt
+        # the same state point with FP32 depletant predicates and the FP64 guard band
+        s32 = hp.Sim(sp.n, sp.L, sp.seed, sp.replica_id, precision=hp.FP32_GUARDED)
+        s32.set_shape(sp.kind, sp.params)
+        s32.set_fugacity(sp.z_p, sp.d_dep, sp.n_trial)
+        s32.set_moves(sp.d_trans, sp.a_rot, sp.p_rot)
+        pq, qq, _ = sim.get_state()
+        s32.set_state(pq, qq)
+        if tuning:
+            s32.set_tuning(tuning["cells_per_wave"], tuning["waves_per_block"], tuning["max_waves"])
+        t3, _, _, dt3 = _timed_sweeps(torch, s32, args.steps, 3)
+        fp32[str(eta)] = {"moves_per_s": t3["trials"] / dt3, "fp64_fallbacks": t3["fp64_fallbacks"],
+                          "fp64_fallbacks_per_depletant": t3["fp64_fallbacks"] / max(t3["depletants_drawn"], 1)}
+        s32.close()
     d = _line(moves / secs, {"depletants_resolved": checks, "accepts": 1, "trials": 1}, secs, 4 * args.steps,
               3, "hemispheres N=16384 phi_c=0.20 q=0.15 eta_r in {0.1,0.2,0.3,0.4}, p_rot=0.5, FP64",
-              {"per_eta_r": per, "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))})
+              {"per_eta_r": per, "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+               "fp32_guarded_per_eta_r": fp32})
     d.pop("acceptance")
     return d
 

@@ -258,7 +258,14 @@ Params make_params(const hpmc_sim* s)
     {
         // sigma = the colloid's circumdiameter
         double eps = 1e-5 * (2.0 * s->S.rcirc);
+        // spheres: band of |v|^2 around R0^2; oriented shapes: band of the
+        // distance to the core around r_dep (hemisphere) or r_s + r_dep (swept disk)
+        double thr = s->S.kind == HPMC_DISCOID ? s->S.rs + 0.5 * s->d_dep : 0.5 * s->d_dep;
         double lo = (s->R0 - eps) * (s->R0 - eps), hi = (s->R0 + eps) * (s->R0 + eps);
+        if (s->S.oriented) {
+            lo = thr - eps;
+            hi = thr + eps;
+        }
         P.g_lo = nextafterf(static_cast<float>(lo), 0.0f);
         P.g_hi = nextafterf(static_cast<float>(hi), INFINITY);
     }

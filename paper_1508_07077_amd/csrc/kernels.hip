@@ -232,16 +232,74 @@ __device__ inline void get_entry(const Params& P, const Work& W, const WaveCtx& 
     }
 }
 
-// wave-cooperative: does a depletant at offset e overlap any stencil colloid?
+// --- FP32 with an FP64 guard band for the oriented depletant predicates ----
+struct Mat3f {
+    float m[9];
+};
+
+__device__ inline Mat3f to_f32(const Mat3& R)
+{
+    Mat3f r;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) r.m[k] = static_cast<float>(R.m[k]);
+    return r;
+}
+
+// distance from the body-frame point p to the shape's core (hemisphere: the
+// half ball, <= 0 inside it; swept disk: the bare disk), in FP32.  The
+// depletant overlaps exactly when this distance is below r_dep (hemisphere)
+// or r_s + r_dep (swept disk); the branch formulas agree on the branch
+// boundaries, so an FP32 branch choice off by rounding changes the value only
+// by about the rounding.
 template <int KIND>
-__device__ inline bool stencil_hit_coop(const Params& P, const Work& W, const WaveCtx& c, Vec3 e)
+__device__ inline float core_dist32(const Shape& S, float px, float py, float pz)
+{
+    const float a = static_cast<float>(S.a);
+    const float rho2 = px * px + py * py;
+    if constexpr (KIND == kHemisphere) {
+        if (pz >= 0.0f) return sqrtf(rho2 + pz * pz) - a;
+        if (rho2 <= a * a) return -pz;
+    } else {
+        if (rho2 <= a * a) return fabsf(pz);
+    }
+    const float t = sqrtf(rho2) - a;
+    return sqrtf(t * t + pz * pz);
+}
+
+// Depletant at world offset v from a colloid with rotation R: FP64 (the
+// contract) or FP32 decided outside a band of 1e-5 sigma around the threshold
+// (the FP32 error of the distance is below 1e-6 for |v| < 4), FP64 inside it
+// (counted in fb).
+template <int KIND, bool F32>
+__device__ inline bool dep_ov_g(const Params& P, Vec3 v, const Mat3& R, const Mat3f& Rf, unsigned& fb)
+{
+    if constexpr (!F32) {
+        return dep_ov<KIND>(P.S, v, R);
+    } else {
+        const float vx = static_cast<float>(v.x), vy = static_cast<float>(v.y), vz = static_cast<float>(v.z);
+        const float px = (Rf.m[0] * vx + Rf.m[3] * vy) + Rf.m[6] * vz;
+        const float py = (Rf.m[1] * vx + Rf.m[4] * vy) + Rf.m[7] * vz;
+        const float pz = (Rf.m[2] * vx + Rf.m[5] * vy) + Rf.m[8] * vz;
+        const float d = core_dist32<KIND>(P.S, px, py, pz);
+        if (d < P.g_lo) return true;
+        if (d > P.g_hi) return false;
+        ++fb;
+        return dep_ov<KIND>(P.S, v, R);
+    }
+}
+
+// wave-cooperative: does a depletant at offset e overlap any stencil colloid?
+template <int KIND, bool F32 = false>
+__device__ inline bool stencil_hit_coop(const Params& P, const Work& W, const WaveCtx& c, Vec3 e, unsigned& fb)
 {
     bool hit = false;
     for (int i = lane_id(); i < c.nst; i += 64) {
         Vec3 D;
         Mat3 R;
         get_entry<KIND>(P, W, c, i, D, R);
-        hit = hit || dep_ov<KIND>(P.S, e - D, R);
+        Mat3f Rf{};
+        if constexpr (F32) Rf = to_f32(R);
+        hit = hit || dep_ov_g<KIND, F32>(P, e - D, R, Rf, fb);
     }
     return __ballot(hit) != 0ull;
 }
@@ -556,9 +614,10 @@ __global__ void scatter_back_kernel(const Desc* __restrict__ D, int advance)
 // ---------------------------------------------------------------------------
 // one colour of the checkerboard: every active cell runs its trials
 // ---------------------------------------------------------------------------
-template <int KIND>
+template <int KIND, bool F32>
 __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int phase)
 {
+    unsigned fb = 0;  // FP64 fallbacks of the guarded FP32 depletant tests (this lane)
     extern __shared__ __align__(16) unsigned char smem[];
     double* sF = reinterpret_cast<double*>(smem);
     int* sG = reinterpret_cast<int*>(smem + kPoissonK * sizeof(double));
@@ -744,6 +803,11 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
                     Rn = quat_to_mat(qn[0], qn[1], qn[2], qn[3]);
                     Ro = quat_to_mat(qj.x, qj.y, qj.z, qj.w);
                 }
+                Mat3f Rn32{}, Ro32{};
+                if constexpr (F32) {
+                    Rn32 = to_f32(Rn);
+                    Ro32 = to_f32(Ro);
+                }
                 // --- hard colloid overlap: min(1, exp(-beta dH_cc)) ---------------
                 bool hit = false, nearc = false;
                 int checks = 0;
@@ -791,12 +855,12 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
                         bool v0 = acc0 && k0 < Np, v1 = acc1 && k1 < Np;
                         // irrelevant (misses M') or ignored by the old pose
                         if (v0) {
-                            if constexpr (ORI) v0 = dep_ov<KIND>(P.S, e0, Rn);
-                            if (v0) v0 = !dep_ov<KIND>(P.S, e0 - Dold, Ro);
+                            if constexpr (ORI) v0 = dep_ov_g<KIND, F32>(P, e0, Rn, Rn32, fb);
+                            if (v0) v0 = !dep_ov_g<KIND, F32>(P, e0 - Dold, Ro, Ro32, fb);
                         }
                         if (v1) {
-                            if constexpr (ORI) v1 = dep_ov<KIND>(P.S, e1, Rn);
-                            if (v1) v1 = !dep_ov<KIND>(P.S, e1 - Dold, Ro);
+                            if constexpr (ORI) v1 = dep_ov_g<KIND, F32>(P, e1, Rn, Rn32, fb);
+                            if (v1) v1 = !dep_ov_g<KIND, F32>(P, e1 - Dold, Ro, Ro32, fb);
                         }
                         unsigned long long r0 = __ballot(v0), r1 = __ballot(v1);
                         // survivors in ascending depletant index: lane order, candidate 0 before 1
@@ -827,7 +891,7 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
                                 }
                                 ignored = __ballot(h) != 0ull;
                             } else {
-                                ignored = stencil_hit_coop<KIND>(P, W, c, es);
+                                ignored = stencil_hit_coop<KIND, F32>(P, W, c, es, fb);
                             }
                             if (ignored) continue;
                             // blocking: free in M, overlapping M'
@@ -918,6 +982,7 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
         }
         wave_sync();
     }
+    cnt[cFp64Fallbacks] += static_cast<unsigned long long>(wave_sum(static_cast<int>(fb)));
     if (lane == 0) {
         unsigned long long* dst = W.counters + static_cast<size_t>(gw % kCounterCopies) * kCounterStride;
 #pragma unroll
@@ -1458,13 +1523,14 @@ __global__ __launch_bounds__(64 * kSmallWaves) void sweep_small_kernel(const Des
     if (tid == 0) *W.sweep_dev = sweep0 + static_cast<uint32_t>(n_sweeps);
 }
 
-template <int KIND>
+// F32: depletant predicates in FP32 with the FP64 guard band
+template <int KIND, bool F32>
 __global__ __launch_bounds__(256) void phase_oriented_kernel(const Desc* __restrict__ D, int phase)
 {
     Params P = D[blockIdx.y].P;
     const Work W = D[blockIdx.y].W;
     P.sweep = *W.sweep_dev;
-    phase_body<KIND>(P, W, phase);
+    phase_body<KIND, F32>(P, W, phase);
 }
 
 __global__ void reduce_counters_kernel(const Desc* __restrict__ D)
@@ -1782,10 +1848,14 @@ hipError_t launch_phase(const Group& g, int phase, hipStream_t stream)
         int waves = g.maxActive < g.max_waves ? g.maxActive : g.max_waves;
         if (R > 1 && waves > 512) waves = 512;
         dim3 grid(blocks_for(waves, g.wpb), R);
-        if (g.kind == kHemisphere)
-            hipLaunchKernelGGL(phase_oriented_kernel<kHemisphere>, grid, bs, g.lds, stream, g.d, phase);
+        if (g.kind == kHemisphere && g.precision == 1)
+            hipLaunchKernelGGL((phase_oriented_kernel<kHemisphere, true>), grid, bs, g.lds, stream, g.d, phase);
+        else if (g.kind == kHemisphere)
+            hipLaunchKernelGGL((phase_oriented_kernel<kHemisphere, false>), grid, bs, g.lds, stream, g.d, phase);
+        else if (g.precision == 1)
+            hipLaunchKernelGGL((phase_oriented_kernel<kDiscoid, true>), grid, bs, g.lds, stream, g.d, phase);
         else
-            hipLaunchKernelGGL(phase_oriented_kernel<kDiscoid>, grid, bs, g.lds, stream, g.d, phase);
+            hipLaunchKernelGGL((phase_oriented_kernel<kDiscoid, false>), grid, bs, g.lds, stream, g.d, phase);
     }
     return hipGetLastError();
 }

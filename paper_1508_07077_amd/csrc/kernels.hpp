@@ -54,7 +54,7 @@ struct Params {
     double s_ball;  // R0 * 2^-21
     int shell;      // depletants in the shell r_inner <= |e| < R0 instead of the ball
     double r_inner, span;  // span = R0 - r_inner
-    float g_lo, g_hi;      // FP32 guard band: (R0 - eps)^2 rounded down, (R0 + eps)^2 rounded up, eps = 1e-5 sigma
+    float g_lo, g_hi;      // FP32 guard band (eps = 1e-5 sigma): spheres (R0 -+ eps)^2, oriented shapes thr -+ eps, rounded outward
     // per-wave LDS layout of the phase kernel
     int list_cap, own_cap, geo_cap;
     int wave_lds;       // bytes per wave

@@ -31,3 +31,19 @@ def test_c3_shaped_fp32_guarded(region):
     # more often in the thin shell, whose points all lie near the old pose's surface
     rate = 1e-4 if region == 0 else 1e-2
     assert tot["fp64_fallbacks"] < rate * tot["depletants_drawn"] + 10
+
+
+@pytest.mark.parametrize("kind", [wl.HEMISPHERE, wl.DISCOID])
+def test_oriented_fp32_guarded(kind):
+    """hemisphere and swept-disk depletant predicates in FP32 with the guard band"""
+    if kind == wl.HEMISPHERE:
+        sp = wl.StatePoint(kind, (1.0,), 400, 0.20, 0.15, 0.30, n_trial=0, d_trans=0.05, a_rot=0.05, p_rot=0.5,
+                           seed=61)
+    else:
+        sp = wl.StatePoint(kind, (0.5, 0.1), 300, 0.25, 0.2, 0.30, n_trial=2, d_trans=0.04, a_rot=0.04, p_rot=0.5,
+                           seed=62)
+    pos, quat = _melt(sp, 10)
+    g, o = make_pair(sp, pos, quat, precision=FP32_GUARDED)
+    tot, div = compare_sweeps(g, o, 6, allow_near=True)
+    assert div <= 1 and tot["accepts"] > 0
+    assert tot["fp64_fallbacks"] < 1e-3 * tot["depletants_drawn"] + 10
