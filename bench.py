@@ -56,9 +56,9 @@ def shell_ops_per_check(R0: float, r_i: float) -> float:
 # work.  HBM bytes per launch from two rocprofv3 passes (FETCH_SIZE,
 # WRITE_SIZE) scaled by the same counters over a plain 256 MiB device copy.
 # Both hold only for the kernel sources with this digest.
-PROFILED_KERNEL_DIGEST = "c0e12651e4900661"
+PROFILED_KERNEL_DIGEST = "7b7505d30d7d158d"
 CALIBRATED_OPS_PER_CHECK = 263.35
-PROFILED_TRAFFIC_BYTES = {"ball": 109906051, "shell": 110440627}
+PROFILED_TRAFFIC_BYTES = {"ball": 109906990, "shell": 110441240}
 
 
 def kernel_digest() -> str:
