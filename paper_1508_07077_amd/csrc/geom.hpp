@@ -114,21 +114,26 @@ __host__ __device__ inline bool dep_overlap(const Shape& S, Vec3 v, const Mat3& 
 // ---------------------------------------------------------------------------
 __host__ __device__ inline Vec3 support_body(const Shape& S, Vec3 n)
 {
-    double rho = sqrt(n.x * n.x + n.y * n.y);
+    // unit directions by reciprocal square roots: no divisions in the MPR loop
+    double rho2 = n.x * n.x + n.y * n.y;
     if (S.kind == kHemisphere) {
         if (n.z > 0.0) {
-            double inv = S.a / sqrt(dot(n, n));
+            double inv = S.a * rsqrt(dot(n, n));
             return v3(n.x * inv, n.y * inv, n.z * inv);
         }
-        if (rho > 0.0) return v3(S.a * n.x / rho, S.a * n.y / rho, 0.0);
+        if (rho2 > 0.0) {
+            double inv = S.a * rsqrt(rho2);
+            return v3(n.x * inv, n.y * inv, 0.0);
+        }
         return v3(0.0, 0.0, 0.0);
     }
     // discoid: disk support + ball support
-    double nn = sqrt(dot(n, n));
-    Vec3 s = v3(S.rs * n.x / nn, S.rs * n.y / nn, S.rs * n.z / nn);
-    if (rho > 0.0) {
-        s.x = s.x + S.a * n.x / rho;
-        s.y = s.y + S.a * n.y / rho;
+    double inv_n = S.rs * rsqrt(dot(n, n));
+    Vec3 s = v3(n.x * inv_n, n.y * inv_n, n.z * inv_n);
+    if (rho2 > 0.0) {
+        double inv_r = S.a * rsqrt(rho2);
+        s.x = s.x + n.x * inv_r;
+        s.y = s.y + n.y * inv_r;
     }
     return s;
 }
