@@ -209,12 +209,15 @@ __host__ __device__ inline PairResult mpr_overlap(const Shape& S, Vec3 d, const 
             return res;
         }
         Vec3 v4 = HPMC_SUP(n);
-        double nn = sqrt(dot(n, n));
-        if (dot(v4, n) <= 0.0) {
-            res.near = (-dot(v4, n) < 1e-9 * nn);
+        // tolerances relative to |n|, compared in squares (no square root per step)
+        const double n2 = dot(n, n);
+        const double s4 = dot(v4, n);
+        if (s4 <= 0.0) {
+            res.near = s4 * s4 < 1e-18 * n2;
             return res;
         }
-        if (dot(v4 - v3p, n) <= tol * nn || dot(v4 - v1, n) <= tol * nn || dot(v4 - v2, n) <= tol * nn) {
+        auto within = [&](double t) { return t <= 0.0 || t * t <= (tol * tol) * n2; };
+        if (within(dot(v4 - v3p, n)) || within(dot(v4 - v1, n)) || within(dot(v4 - v2, n))) {
             // support plane within tolerance of the portal: contact within rounding
             res.near = true;
             res.overlap = false;
