@@ -269,15 +269,13 @@ Params make_params(const hpmc_sim* s)
         P.g_lo = nextafterf(static_cast<float>(lo), 0.0f);
         P.g_hi = nextafterf(static_cast<float>(hi), INFINITY);
     }
-    // per-wave LDS of the phase kernel: rigorous packing bounds (hard bodies
-    // are disjoint) for the stencil list and own-cell records
+    // per-wave LDS of the phase kernel: a rigorous packing bound (hard bodies
+    // are disjoint) for the stencil list
     double rc2 = 2.0 * s->S.rcirc;
     int64_t list_cap = (s->n == 2) ? s->N : packing_bound(s, 3.0 * s->w + rc2);
-    int64_t own_cap = (s->n == 2) ? s->N : packing_bound(s, s->w + rc2);
     int gs = s->S.oriented ? 12 : 3;
     int64_t geo_cap = s->S.oriented ? std::min<int64_t>(list_cap, 96) : std::min<int64_t>(list_cap, 512);
     P.list_cap = static_cast<int>(list_cap);
-    P.own_cap = static_cast<int>(own_cap);
     P.geo_cap = static_cast<int>(geo_cap);
     if (!s->S.oriented) {
         // spheres: two stage buffers, each the stencil list + staged records (x, y) and (z, index)
@@ -288,20 +286,34 @@ Params make_params(const hpmc_sim* s)
         o = align256(o + 64 * 16);
         P.off_geo = 0;
         P.wave_lds = static_cast<int>(2 * o);
-        P.own_cap = 64;
         int wpb = s->tune_wpb ? s->tune_wpb : 4;
         while (wpb > 1 && kTableLds + static_cast<size_t>(wpb) * P.wave_lds > 64 * 1024) wpb >>= 1;
         P.waves_per_block = wpb;
         P.chunk = s->tune_chunk ? s->tune_chunk : kChunk;
         return P;
     }
+    // oriented shapes: the stencil list, the geometry cache and the per-trial
+    // close and reach lists (the cell's own records stay in HBM)
     size_t off = align256(static_cast<size_t>(list_cap) * 4);
-    P.off_own_pos = static_cast<int>(off);
-    off = align256(off + static_cast<size_t>(own_cap) * 32);
-    P.off_own_q = static_cast<int>(off);
-    if (s->S.oriented) off = align256(off + static_cast<size_t>(own_cap) * 32);
     P.off_geo = static_cast<int>(off);
     off = align256(off + static_cast<size_t>(geo_cap) * 8 * gs);
+    {
+        // A colloid whose reference point lies within 2 r_circ of the proposed
+        // one has its body inside the cube of side 6 r_circ around it; one that
+        // a depletant point of B(x', R0) or a CB trial point of B(x, R0) can
+        // overlap lies within reach of x', its body within the cube of side
+        // 2 reach + 2 r_circ.  Hard bodies are disjoint, so both counts obey
+        // the packing bound.
+        const double rc = s->S.rcirc;
+        const double reach = s->R0 + rc + 0.5 * s->d_dep + 1.7320508075688772 * s->d_trans * (1.0 + 1e-12) + 1e-9;
+        P.reach_sq = reach * reach;
+        P.close_cap = static_cast<int>(std::min<int64_t>(list_cap, packing_bound(s, 6.0 * rc)));
+        P.reach_cap = static_cast<int>(std::min<int64_t>(list_cap, packing_bound(s, 2.0 * reach + 2.0 * rc)));
+        P.off_close = static_cast<int>(off);
+        off = align256(off + static_cast<size_t>(P.close_cap) * 4);
+        P.off_reach = static_cast<int>(off);
+        off = align256(off + static_cast<size_t>(P.reach_cap) * 4);
+    }
     P.wave_lds = static_cast<int>(off);
     int wpb = s->tune_wpb ? s->tune_wpb : 4;
     while (wpb > 1 && kTableLds + static_cast<size_t>(wpb) * off > 64 * 1024) wpb >>= 1;

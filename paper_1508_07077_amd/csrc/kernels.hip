@@ -177,17 +177,24 @@ __device__ inline bool ball4(Words w, double m[4])
     return s < 0x1p50;
 }
 
-// per-wave working set of the phase kernel
+// per-wave working set of the phase kernel.  The cell's own records are
+// updated in place in the cell-ordered arrays: during a phase only the wave
+// that runs a cell reads or writes its members (neighbouring cells of the same
+// colour are two cells apart), so no other wave sees them change.
 struct WaveCtx {
     int* list;          // stencil slots
-    double4* own_pos;   // own-cell records (updated on accept)
-    double4* own_q;
     double* geo;        // per-cell geometry cache: position (3) [+ R (9)] per entry
+    int* close;         // per trial: entries whose circumsphere meets the proposed pose's
+    int* reach;         // per trial: entries a depletant or CB trial point can overlap
     int start, nc, nst;
     int jslot;
     int jl;             // list index of the moved colloid (own members come first)
+    int nr;             // entries in reach (all nst of them when rl is null)
+    const int* rl;      // reach, or null when the list overflowed its bound
     Vec3 xn;
 };
+
+__device__ inline int reach_entry(const WaveCtx& c, int k) { return c.rl ? c.rl[k] : k; }
 
 template <int KIND>
 struct Traits {
@@ -195,24 +202,35 @@ struct Traits {
     static constexpr int geo_stride = oriented ? 12 : 3;
 };
 
+// stencil entry i's reference point relative to the proposed position (the
+// moved colloid's own entry reads as far away)
+template <int KIND>
+__device__ inline Vec3 get_offset(const Params& P, const Work& W, const WaveCtx& c, int i)
+{
+    double4 p;
+    if (i == c.jl) return v3(kFar, kFar, kFar);
+    if (i < P.geo_cap) {
+        const double* g = c.geo + static_cast<size_t>(i) * Traits<KIND>::geo_stride;
+        p = make_double4(g[0], g[1], g[2], 0.0);
+    } else {
+        p = W.rpos[c.list[i]];
+    }
+    return v3(mi(P, p.x - c.xn.x), mi(P, p.y - c.xn.y), mi(P, p.z - c.xn.z));
+}
+
 // geometry of stencil entry i relative to the proposed position
 template <int KIND>
 __device__ inline void load_entry(const Params& P, const Work& W, const WaveCtx& c, int i, Vec3& D, Mat3& R)
 {
-    int slot = c.list[i];
-    double4 p, q;
-    bool own = slot >= c.start && slot < c.start + c.nc;
-    if (own)
-        p = c.own_pos[slot - c.start];
-    else
-        p = W.rpos[slot];
+    const int slot = c.list[i];
+    const double4 p = W.rpos[slot];
     if (slot == c.jslot) {
         D = v3(kFar, kFar, kFar);
     } else {
         D = v3(mi(P, p.x - c.xn.x), mi(P, p.y - c.xn.y), mi(P, p.z - c.xn.z));
     }
     if constexpr (Traits<KIND>::oriented) {
-        q = own ? c.own_q[slot - c.start] : W.rquat[slot];
+        const double4 q = W.rquat[slot];
         R = quat_to_mat(q.x, q.y, q.z, q.w);
     }
 }
@@ -288,15 +306,16 @@ __device__ inline bool dep_ov_g(const Params& P, Vec3 v, const Mat3& R, const Ma
     }
 }
 
-// wave-cooperative: does a depletant at offset e overlap any stencil colloid?
+// wave-cooperative: does a depletant at offset e overlap any stencil colloid
+// (those in reach: no other can)?
 template <int KIND, bool F32 = false>
 __device__ inline bool stencil_hit_coop(const Params& P, const Work& W, const WaveCtx& c, Vec3 e, unsigned& fb)
 {
     bool hit = false;
-    for (int i = lane_id(); i < c.nst; i += 64) {
+    for (int k = lane_id(); k < c.nr; k += 64) {
         Vec3 D;
         Mat3 R;
-        get_entry<KIND>(P, W, c, i, D, R);
+        get_entry<KIND>(P, W, c, reach_entry(c, k), D, R);
         Mat3f Rf{};
         if constexpr (F32) Rf = to_f32(R);
         hit = hit || dep_ov_g<KIND, F32>(P, e - D, R, Rf, fb);
@@ -304,17 +323,17 @@ __device__ inline bool stencil_hit_coop(const Params& P, const Work& W, const Wa
     return __ballot(hit) != 0ull;
 }
 
-// per-lane: does the point p overlap any stencil colloid?  (all lanes read the
-// same entry at the same time: LDS broadcast)
+// per-lane: does the point p overlap any stencil colloid in reach?  (all lanes
+// read the same entry at the same time: LDS broadcast)
 template <int KIND>
 __device__ inline bool stencil_hit_lane(const Params& P, const Work& W, const WaveCtx& c, Vec3 p, bool active)
 {
     bool hit = !active;
-    for (int i = 0; i < c.nst; ++i) {
+    for (int k = 0; k < c.nr; ++k) {
         if (__ballot(!hit) == 0ull) break;
         Vec3 D;
         Mat3 R;
-        get_entry<KIND>(P, W, c, i, D, R);
+        get_entry<KIND>(P, W, c, reach_entry(c, k), D, R);
         if (!hit) hit = dep_ov<KIND>(P.S, p - D, R);
     }
     return hit && active;
@@ -631,11 +650,12 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
     unsigned char* wbase = smem + kTableLds + static_cast<size_t>(wv) * P.wave_lds;
     WaveCtx c;
     c.list = reinterpret_cast<int*>(wbase);
-    c.own_pos = reinterpret_cast<double4*>(wbase + P.off_own_pos);
-    c.own_q = reinterpret_cast<double4*>(wbase + P.off_own_q);
     c.geo = reinterpret_cast<double*>(wbase + P.off_geo);
+    c.close = reinterpret_cast<int*>(wbase + P.off_close);
+    c.reach = reinterpret_cast<int*>(wbase + P.off_reach);
     constexpr int GS = Traits<KIND>::geo_stride;
     constexpr bool ORI = Traits<KIND>::oriented;
+    static_assert(ORI, "spheres run phase_sphere_body");
 
     unsigned long long cnt[kNumCounters];
 #pragma unroll
@@ -654,15 +674,6 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
         c.start = W.cell_start[C];
         c.nc = W.cell_start[C + 1] - c.start;
         if (c.nc == 0) continue;
-        if (c.nc > P.own_cap) {
-            if (lane == 0) atomicOr(W.flags, kFlagOwnOverflow);
-            continue;
-        }
-        // own-cell records into LDS (they change as moves are accepted)
-        for (int i = lane; i < c.nc; i += 64) {
-            c.own_pos[i] = W.rpos[c.start + i];
-            if constexpr (ORI) c.own_q[i] = W.rquat[c.start + i];
-        }
         // stencil: the de-duplicated 27 (n > 2) or 8 (n = 2) cells around C
         int es = 0, ec = 0;
         if (nb.on) {
@@ -685,15 +696,14 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
         {
             const int ng = c.nst < P.geo_cap ? c.nst : P.geo_cap;
             for (int i = lane; i < ng; i += 64) {
-                int slot = c.list[i];
-                bool own = slot >= c.start && slot < c.start + c.nc;
-                double4 pp = own ? c.own_pos[slot - c.start] : W.rpos[slot];
+                const int slot = c.list[i];
+                const double4 pp = W.rpos[slot];
                 double* g = c.geo + static_cast<size_t>(i) * GS;
                 g[0] = pp.x;
                 g[1] = pp.y;
                 g[2] = pp.z;
                 if constexpr (ORI) {
-                    double4 qq = own ? c.own_q[slot - c.start] : W.rquat[slot];
+                    const double4 qq = W.rquat[slot];
                     Mat3 R = quat_to_mat(qq.x, qq.y, qq.z, qq.w);
 #pragma unroll
                     for (int k = 0; k < 9; ++k) g[3 + k] = R.m[k];
@@ -725,9 +735,9 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
             const bool rotate = ORI && P.p_rot > 0.0 && u01(sel1) < P.p_rot;
             c.jslot = c.start + jl;
             c.jl = jl;
-            const double4 pj = c.own_pos[jl];
+            const double4 pj = W.rpos[c.jslot];
             double4 qj = make_double4(1.0, 0.0, 0.0, 0.0);
-            if constexpr (ORI) qj = c.own_q[jl];
+            if constexpr (ORI) qj = W.rquat[c.jslot];
             Vec3 xn = v3(pj.x, pj.y, pj.z);
             double qn[4] = {qj.x, qj.y, qj.z, qj.w};
             if (!rotate) {
@@ -789,15 +799,37 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
             if (cell_of(P, xn.x, xn.y, xn.z, g0, g1, g2) != C) {
                 o.reason = 1;
             } else {
-                // stencil entries beyond the cache: lane i keeps entry i in registers
-                // (survivor tests of the unoriented instantiation)
-                Vec3 Dreg = v3(kFar, kFar, kFar);
-                if constexpr (!ORI) {
-                    if (lane < c.nst) {
-                        Mat3 R;
-                        get_entry<KIND>(P, W, c, lane, Dreg, R);
+                // A stencil of more than one entry per lane: one pass over it builds
+                // the close list (circumspheres of the proposed pose and the entry
+                // meet, so the pair needs the narrow phase) and the reach list (a
+                // depletant of V_0 or a CB trial point can overlap the entry), both
+                // in ascending entry order, so that the narrow phase and the
+                // depletant tests take one round instead of one per 64 entries.
+                // A smaller stencil is taken whole: it is one round either way.
+                int ncl = 0, nrc = 0;
+                const int nlist = c.nst > 64 ? c.nst : 0;
+                for (int i0 = 0; i0 < nlist; i0 += 64) {
+                    const int i = i0 + lane;
+                    bool cl = false, rc = false;
+                    if (i < c.nst) {
+                        const Vec3 D = get_offset<KIND>(P, W, c, i);
+                        const double dd = dot(D, D);
+                        cl = dd < P.S.lim_sq;
+                        rc = dd < P.reach_sq;
                     }
+                    const unsigned long long mc = __ballot(cl), mr = __ballot(rc);
+                    const int kc = ncl + bits_below(mc), kr = nrc + bits_below(mr);
+                    if (cl && kc < P.close_cap) c.close[kc] = i;
+                    if (rc && kr < P.reach_cap) c.reach[kr] = i;
+                    ncl += __popcll(mc);
+                    nrc += __popcll(mr);
                 }
+                if (nlist) wave_sync();
+                // a list beyond its packing bound (impossible for disjoint bodies) falls back to every entry
+                const int* cl_list = (nlist && ncl <= P.close_cap) ? c.close : nullptr;
+                const int n_close = cl_list ? ncl : c.nst;
+                c.rl = (nlist && nrc <= P.reach_cap) ? c.reach : nullptr;
+                c.nr = c.rl ? nrc : c.nst;
                 Mat3 Rn, Ro;
                 if constexpr (ORI) {
                     Rn = quat_to_mat(qn[0], qn[1], qn[2], qn[3]);
@@ -811,10 +843,10 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
                 // --- hard colloid overlap: min(1, exp(-beta dH_cc)) ---------------
                 bool hit = false, nearc = false;
                 int checks = 0;
-                for (int i = lane; i < c.nst; i += 64) {
+                for (int k = lane; k < n_close; k += 64) {
                     Vec3 D;
                     Mat3 R;
-                    get_entry<KIND>(P, W, c, i, D, R);
+                    get_entry<KIND>(P, W, c, cl_list ? cl_list[k] : k, D, R);
                     PairResult pr = pair_ov<KIND>(P.S, D, Rn, R);
                     hit = hit || pr.overlap;
                     nearc = nearc || pr.near;
@@ -880,20 +912,7 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
                             Vec3 es = cand ? e1 : e0;
                             es = v3(rdlane_d(es.x, src), rdlane_d(es.y, src), rdlane_d(es.z, src));
                             uint32_t ks = rdlane_u(cand ? k1 : k0, src);
-                            bool ignored;
-                            if constexpr (!ORI) {
-                                bool h = dep_ov<KIND>(P.S, es - Dreg, Rn);
-                                for (int i = 64 + lane; i < c.nst; i += 64) {
-                                    Vec3 D;
-                                    Mat3 R;
-                                    get_entry<KIND>(P, W, c, i, D, R);
-                                    h = h || dep_ov<KIND>(P.S, es - D, R);
-                                }
-                                ignored = __ballot(h) != 0ull;
-                            } else {
-                                ignored = stencil_hit_coop<KIND, F32>(P, W, c, es, fb);
-                            }
-                            if (ignored) continue;
+                            if (stencil_hit_coop<KIND, F32>(P, W, c, es, fb)) continue;  // ignored
                             // blocking: free in M, overlapping M'
                             o.nblk++;
                             if (P.n_trial == 0) {
@@ -931,8 +950,8 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
             }
             // --- accept / commit / record ---------------------------------------
             if (o.reason == 0 && lane == 0) {
-                c.own_pos[jl] = make_double4(xn.x, xn.y, xn.z, pj.w);
-                if constexpr (ORI) c.own_q[jl] = make_double4(qn[0], qn[1], qn[2], qn[3]);
+                W.rpos[c.jslot] = make_double4(xn.x, xn.y, xn.z, pj.w);
+                if constexpr (ORI) W.rquat[c.jslot] = make_double4(qn[0], qn[1], qn[2], qn[3]);
                 if (jl < P.geo_cap) {
                     double* g = c.geo + static_cast<size_t>(jl) * GS;
                     g[0] = xn.x;
@@ -975,12 +994,6 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
                        (static_cast<uint32_t>(rotate ? 1 : 0) << 16) | (static_cast<uint32_t>(o.near ? 1 : 0) << 24);
             }
         }
-        // own-cell records back to HBM
-        for (int i = lane; i < c.nc; i += 64) {
-            W.rpos[c.start + i] = c.own_pos[i];
-            if constexpr (ORI) W.rquat[c.start + i] = c.own_q[i];
-        }
-        wave_sync();
     }
     cnt[cFp64Fallbacks] += static_cast<unsigned long long>(wave_sum(static_cast<int>(fb)));
     if (lane == 0) {

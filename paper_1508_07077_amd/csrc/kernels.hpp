@@ -32,7 +32,7 @@ enum CounterIdx : int {
     cFp64Fallbacks,
 };
 
-enum Flags : int { kFlagListOverflow = 1, kFlagOwnOverflow = 2 };
+enum Flags : int { kFlagListOverflow = 1 };
 
 // constants of one state point, passed by value to every kernel
 struct Params {
@@ -56,9 +56,13 @@ struct Params {
     double r_inner, span;  // span = R0 - r_inner
     float g_lo, g_hi;      // FP32 guard band (eps = 1e-5 sigma): spheres (R0 -+ eps)^2, oriented shapes thr -+ eps, rounded outward
     // per-wave LDS layout of the phase kernel
-    int list_cap, own_cap, geo_cap;
+    int list_cap, geo_cap;
     int wave_lds;       // bytes per wave
     int off_own_pos, off_own_q, off_geo;
+    // oriented shapes, per trial: stencil entries whose circumsphere meets the
+    // proposed pose's (close list) and entries a depletant or CB trial can reach
+    int close_cap, reach_cap, off_close, off_reach;
+    double reach_sq;    // (R0 + r_circ + r_dep + sqrt(3) d_trans)^2 plus a margin
     int waves_per_block;
     int chunk;          // spheres: active cells per wave (1..64)
     int active_cells;   // h^3
