@@ -277,6 +277,10 @@ Params make_params(const hpmc_sim* s)
     int64_t geo_cap = s->S.oriented ? std::min<int64_t>(list_cap, 96) : std::min<int64_t>(list_cap, 512);
     P.list_cap = static_cast<int>(list_cap);
     P.geo_cap = static_cast<int>(geo_cap);
+    // A depletant point of B(x', R0) or a CB trial point of B(x, R0) can only
+    // overlap a colloid whose reference point lies within reach of x'.
+    const double reach = s->R0 + s->S.rcirc + 0.5 * s->d_dep + 1.7320508075688772 * s->d_trans * (1.0 + 1e-12) + 1e-9;
+    P.reach_sq = reach * reach;
     if (!s->S.oriented) {
         // spheres: two stage buffers, each the stencil list + staged records (x, y) and (z, index)
         size_t o = align256(static_cast<size_t>(list_cap) * 4);
@@ -299,14 +303,10 @@ Params make_params(const hpmc_sim* s)
     off = align256(off + static_cast<size_t>(geo_cap) * 8 * gs);
     {
         // A colloid whose reference point lies within 2 r_circ of the proposed
-        // one has its body inside the cube of side 6 r_circ around it; one that
-        // a depletant point of B(x', R0) or a CB trial point of B(x, R0) can
-        // overlap lies within reach of x', its body within the cube of side
-        // 2 reach + 2 r_circ.  Hard bodies are disjoint, so both counts obey
-        // the packing bound.
+        // one has its body inside the cube of side 6 r_circ around it; one in
+        // reach, inside the cube of side 2 reach + 2 r_circ.  Hard bodies are
+        // disjoint, so both counts obey the packing bound.
         const double rc = s->S.rcirc;
-        const double reach = s->R0 + rc + 0.5 * s->d_dep + 1.7320508075688772 * s->d_trans * (1.0 + 1e-12) + 1e-9;
-        P.reach_sq = reach * reach;
         P.close_cap = static_cast<int>(std::min<int64_t>(list_cap, packing_bound(s, 6.0 * rc)));
         P.reach_cap = static_cast<int>(std::min<int64_t>(list_cap, packing_bound(s, 2.0 * reach + 2.0 * rc)));
         P.off_close = static_cast<int>(off);

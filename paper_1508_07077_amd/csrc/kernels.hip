@@ -1079,16 +1079,23 @@ __device__ inline int stage_issue(const Params& P, const Work& W, const SphereSt
     return nst;
 }
 
-// does a point at offset p (from x') overlap any stencil colloid?  per lane,
-// entries read from LDS (all lanes read the same entry: broadcast)
+// does a point at offset p (from x') overlap any stencil colloid?  per lane.
+// The staged entries (lane i of Dreg holds entry i's offset) are taken from
+// rmask, the entries in reach of the CB regions, read across lanes; entries
+// beyond the stage from the records.
 __device__ inline bool sphere_hit_lane(const Params& P, const Work& W, const SphereStage& sb, int nst, int jent,
-                                       Vec3 xn, Vec3 p, bool active)
+                                       Vec3 xn, unsigned long long rmask, Vec3 Dreg, Vec3 p, bool active)
 {
     bool hit = !active;
-    for (int i = 0; i < nst; ++i) {
+    for (unsigned long long m = rmask; m; m &= m - 1ull) {
+        const int i = ffs64(m);
+        const Vec3 D = v3(rdlane_d(Dreg.x, i), rdlane_d(Dreg.y, i), rdlane_d(Dreg.z, i));
+        hit = hit || dot(p - D, p - D) < P.S.R0sq;
+    }
+    for (int i = kStage; i < nst; ++i) {
         if (__ballot(!hit) == 0ull) break;
         if (i == jent) continue;
-        double4 r = (i < kStage) ? stage_rec(sb, i) : W.rpos[sb.list[i]];
+        double4 r = W.rpos[sb.list[i]];
         Vec3 D = v3(mi(P, r.x - xn.x), mi(P, r.y - xn.y), mi(P, r.z - xn.z));
         if (!hit) hit = dot(p - D, p - D) < P.S.R0sq;
     }
@@ -1240,6 +1247,8 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
                         hit = hit || dot(D, D) < P.S.dsq;
                     }
                     cnt[cOverlapChecks] += static_cast<unsigned long long>(nst - 1);
+                    // staged entries a CB trial point can reach (the moved colloid's lane holds kFar)
+                    const unsigned long long rmask = __ballot(dot(Dreg, Dreg) < P.reach_sq);
                     if (__ballot(hit) != 0ull) {
                         o.reason = 2;
                     } else if (P.has_dep) {
@@ -1329,8 +1338,8 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
                                     // forward: misses the new pose; reverse: misses the old pose
                                     if (u0) u0 = fwd ? !(dot(p0, p0) < P.S.R0sq) : !(dot(f0 - Dold, f0 - Dold) < P.S.R0sq);
                                     if (u1) u1 = fwd ? !(dot(p1, p1) < P.S.R0sq) : !(dot(f1 - Dold, f1 - Dold) < P.S.R0sq);
-                                    u0 = u0 && !sphere_hit_lane(P, W, S0, nst, jl, xn, p0, u0);
-                                    u1 = u1 && !sphere_hit_lane(P, W, S0, nst, jl, xn, p1, u1);
+                                    u0 = u0 && !sphere_hit_lane(P, W, S0, nst, jl, xn, rmask, Dreg, p0, u0);
+                                    u1 = u1 && !sphere_hit_lane(P, W, S0, nst, jl, xn, rmask, Dreg, p1, u1);
                                     const unsigned long long V0 = __ballot(u0), V1 = __ballot(u1);
                                     Wf += static_cast<uint32_t>(__popcll(V0 & lo_half) + __popcll(V1 & lo_half));
                                     Wr += static_cast<uint32_t>(__popcll(V0 & ~lo_half) + __popcll(V1 & ~lo_half));
