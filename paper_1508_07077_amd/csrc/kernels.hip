@@ -966,14 +966,13 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
             }
             wave_sync();
             cnt[cTrials] += 1;
-            switch (o.reason) {
-            case 0: cnt[cAccepts] += 1; break;
-            case 1: cnt[cRejCellExit] += 1; break;
-            case 2: cnt[cRejOverlap] += 1; break;
-            case 3: cnt[cRejDepletant] += 1; break;
-            case 4: cnt[cRejCbZero] += 1; break;
-            default: cnt[cRejCbMetro] += 1; break;
-            }
+            // one compare per reason, no branch and no indexed select over the counters
+            cnt[cAccepts] += o.reason == 0 ? 1ull : 0ull;
+            cnt[cRejCellExit] += o.reason == 1 ? 1ull : 0ull;
+            cnt[cRejOverlap] += o.reason == 2 ? 1ull : 0ull;
+            cnt[cRejDepletant] += o.reason == 3 ? 1ull : 0ull;
+            cnt[cRejCbZero] += o.reason == 4 ? 1ull : 0ull;
+            cnt[cRejCbMetro] += o.reason == 5 ? 1ull : 0ull;
             cnt[cDrawn] += o.n_dep;
             cnt[cResolved] += o.resolved;
             cnt[cCbTrials] += o.cbt;
@@ -1375,14 +1374,13 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
                 }
                 wave_sync();
                 cnt[cTrials] += 1;
-                switch (o.reason) {
-                case 0: cnt[cAccepts] += 1; break;
-                case 1: cnt[cRejCellExit] += 1; break;
-                case 2: cnt[cRejOverlap] += 1; break;
-                case 3: cnt[cRejDepletant] += 1; break;
-                case 4: cnt[cRejCbZero] += 1; break;
-                default: cnt[cRejCbMetro] += 1; break;
-                }
+                // one compare per reason, no branch and no indexed select over the counters
+                cnt[cAccepts] += o.reason == 0 ? 1ull : 0ull;
+                cnt[cRejCellExit] += o.reason == 1 ? 1ull : 0ull;
+                cnt[cRejOverlap] += o.reason == 2 ? 1ull : 0ull;
+                cnt[cRejDepletant] += o.reason == 3 ? 1ull : 0ull;
+                cnt[cRejCbZero] += o.reason == 4 ? 1ull : 0ull;
+                cnt[cRejCbMetro] += o.reason == 5 ? 1ull : 0ull;
                 cnt[cDrawn] += o.n_dep;
                 cnt[cResolved] += o.resolved;
                 cnt[cCbTrials] += o.cbt;

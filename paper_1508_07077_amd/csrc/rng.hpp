@@ -51,7 +51,7 @@ __device__ inline uint32_t xor3(uint32_t a, uint32_t b, uint32_t k)
 }
 
 // Philox4x32-10 (Salmon et al., SC'11): per round two 32x32->64 multiplies
-// and two three-way XORs; the key schedule stays in scalar registers
+// and two three-way XORs; the key schedule runs on the scalar unit
 __device__ inline Words philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
@@ -65,6 +65,9 @@ __device__ inline Words philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c
         c3 = lo0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
+        // the next round key is derived here, two scalar adds, rather than all
+        // twenty kept live across the kernel (which spills scalar registers)
+        asm volatile("" : "+s"(k0), "+s"(k1));
     }
     return Words{c0, c1, c2, c3};
 }
