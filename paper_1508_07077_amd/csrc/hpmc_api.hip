@@ -289,7 +289,8 @@ Params make_params(const hpmc_sim* s)
         P.off_own_q = static_cast<int>(o);
         o = align256(o + 64 * 16);
         P.off_geo = 0;
-        P.wave_lds = static_cast<int>(2 * o);
+        P.off_cnt = static_cast<int>(2 * o);  // after the two stage buffers: the wave's counters
+        P.wave_lds = static_cast<int>(2 * o + kNumCounters * 8);
         int wpb = s->tune_wpb ? s->tune_wpb : 4;
         while (wpb > 1 && kTableLds + static_cast<size_t>(wpb) * P.wave_lds > 64 * 1024) wpb >>= 1;
         P.waves_per_block = wpb;

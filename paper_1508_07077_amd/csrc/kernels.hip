@@ -1018,7 +1018,7 @@ constexpr int kStage = 64;  // staged stencil entries per cell (more are read fr
 // 1e-6 where |a - b| is near R0, the band is 1.1e-5 wide in |a - b|^2), inside it
 // the FP64 test decides and the fallback is counted.
 template <bool F32>
-__device__ inline bool sphere_in(const Params& P, Vec3 a, Vec3 b, bool active, unsigned long long& fallbacks)
+__device__ inline bool sphere_in(const Params& P, Vec3 a, Vec3 b, bool active, unsigned& fallbacks)
 {
     if constexpr (!F32) return dot(a - b, a - b) < P.S.R0sq;
     float vx = static_cast<float>(a.x) - static_cast<float>(b.x);
@@ -1027,10 +1027,11 @@ __device__ inline bool sphere_in(const Params& P, Vec3 a, Vec3 b, bool active, u
     float q = (vx * vx + vy * vy) + vz * vz;
     bool in = q < P.g_lo;
     bool amb = active && !in && !(q > P.g_hi);
-    unsigned long long m = __ballot(amb);
-    if (m) {
-        fallbacks += static_cast<unsigned long long>(__popcll(m));
-        if (amb) in = dot(a - b, a - b) < P.S.R0sq;
+    if (__ballot(amb)) {
+        if (amb) {
+            ++fallbacks;  // this lane's count: callers may run with some lanes off
+            in = dot(a - b, a - b) < P.S.R0sq;
+        }
     }
     return in;
 }
@@ -1123,14 +1124,16 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
     const int wv = threadIdx.x >> 6;
     unsigned char* wbase = smem + kTableLds + static_cast<size_t>(wv) * P.wave_lds;
     auto stage_buf = [&](int b) {
-        unsigned char* q = wbase + static_cast<size_t>(b) * (P.wave_lds / 2);
+        unsigned char* q = wbase + static_cast<size_t>(b) * (P.off_cnt / 2);
         return SphereStage{reinterpret_cast<int*>(q), reinterpret_cast<double*>(q + P.off_own_pos),
                            reinterpret_cast<double*>(q + P.off_own_q)};
     };
 
-    unsigned long long cnt[kNumCounters];
-#pragma unroll
-    for (int k = 0; k < kNumCounters; ++k) cnt[k] = 0ull;
+    // the wave's counters live in its LDS (uniform values, no registers); lane
+    // 0 adds to them without waiting for the result
+    unsigned long long* wcnt = reinterpret_cast<unsigned long long*>(wbase + P.off_cnt);
+    if (lane < kNumCounters) wcnt[lane] = 0ull;
+    unsigned fallbacks = 0;  // FP64 fallbacks of the guarded FP32 tests (this lane)
 
     const int colour = W.perm[phase];
     const double g0 = W.grid[0], g1 = W.grid[1], g2 = W.grid[2];
@@ -1245,7 +1248,7 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
                         Vec3 D = v3(mi(P, r.x - xn.x), mi(P, r.y - xn.y), mi(P, r.z - xn.z));
                         hit = hit || dot(D, D) < P.S.dsq;
                     }
-                    cnt[cOverlapChecks] += static_cast<unsigned long long>(nst - 1);
+                    if (lane == 0) atomicAdd(&wcnt[cOverlapChecks], static_cast<unsigned long long>(nst - 1));
                     // staged entries a CB trial point can reach (the moved colloid's lane holds kFar)
                     const unsigned long long rmask = __ballot(dot(Dreg, Dreg) < P.reach_sq);
                     if (__ballot(hit) != 0ull) {
@@ -1278,8 +1281,8 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
                             uint32_t k1 = k0 + (acc0 ? 1u : 0u);
                             // ignored by the old pose (every ball point overlaps the new pose)
                             bool v0 = acc0 && k0 < Np, v1 = acc1 && k1 < Np;
-                            v0 = v0 && !sphere_in<F32>(P, e0, Dold, v0, cnt[cFp64Fallbacks]);
-                            v1 = v1 && !sphere_in<F32>(P, e1, Dold, v1, cnt[cFp64Fallbacks]);
+                            v0 = v0 && !sphere_in<F32>(P, e0, Dold, v0, fallbacks);
+                            v1 = v1 && !sphere_in<F32>(P, e1, Dold, v1, fallbacks);
                             unsigned long long r0 = __ballot(v0), r1 = __ballot(v1);
                             while ((r0 | r1) && !done) {
                                 int l0 = r0 ? ffs64(r0) : 64, l1 = r1 ? ffs64(r1) : 64;
@@ -1297,7 +1300,7 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
                                 Vec3 es3 = cand ? e1 : e0;
                                 es3 = v3(rdlane_d(es3.x, src), rdlane_d(es3.y, src), rdlane_d(es3.z, src));
                                 uint32_t ks = rdlane_u(cand ? k1 : k0, src);
-                                bool h = sphere_in<F32>(P, es3, Dreg, true, cnt[cFp64Fallbacks]);
+                                bool h = sphere_in<F32>(P, es3, Dreg, true, fallbacks);
                                 for (int i = kStage + lane; i < nst; i += 64) {
                                     double4 r = W.rpos[S0.list[i]];
                                     Vec3 D = v3(mi(P, r.x - xn.x), mi(P, r.y - xn.y), mi(P, r.z - xn.z));
@@ -1373,17 +1376,13 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
                     S0.recB[2 * jl] = xn.z;
                 }
                 wave_sync();
-                cnt[cTrials] += 1;
-                // one compare per reason, no branch and no indexed select over the counters
-                cnt[cAccepts] += o.reason == 0 ? 1ull : 0ull;
-                cnt[cRejCellExit] += o.reason == 1 ? 1ull : 0ull;
-                cnt[cRejOverlap] += o.reason == 2 ? 1ull : 0ull;
-                cnt[cRejDepletant] += o.reason == 3 ? 1ull : 0ull;
-                cnt[cRejCbZero] += o.reason == 4 ? 1ull : 0ull;
-                cnt[cRejCbMetro] += o.reason == 5 ? 1ull : 0ull;
-                cnt[cDrawn] += o.n_dep;
-                cnt[cResolved] += o.resolved;
-                cnt[cCbTrials] += o.cbt;
+                if (lane == 0) {
+                    atomicAdd(&wcnt[cTrials], 1ull);
+                    atomicAdd(&wcnt[cAccepts + o.reason], 1ull);  // reasons 0..5 in counter order
+                    if (o.n_dep) atomicAdd(&wcnt[cDrawn], static_cast<unsigned long long>(o.n_dep));
+                    if (o.resolved) atomicAdd(&wcnt[cResolved], static_cast<unsigned long long>(o.resolved));
+                    if (o.cbt) atomicAdd(&wcnt[cCbTrials], static_cast<unsigned long long>(o.cbt));
+                }
                 if (P.trace && lane == 0) {
                     uint32_t* r = reinterpret_cast<uint32_t*>(static_cast<unsigned char*>(W.trace) +
                                                               (static_cast<size_t>(P.n_select) * start + t) * 40);
@@ -1408,21 +1407,28 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
         buf ^= 1;
     }
     (void)Rnone;
+    if constexpr (F32) {
+        const int fb = wave_sum(static_cast<int>(fallbacks));
+        if (lane == 0 && fb) atomicAdd(&wcnt[cFp64Fallbacks], static_cast<unsigned long long>(fb));
+    }
+    wave_sync();
     if (lane == 0) {
         unsigned long long* dst = W.counters + static_cast<size_t>(gw % kCounterCopies) * kCounterStride;
 #pragma unroll
-        for (int k = 0; k < kNumCounters; ++k)
-            if (cnt[k]) atomicAdd(dst + k, cnt[k]);
+        for (int k = 0; k < kNumCounters; ++k) {
+            const unsigned long long v = wcnt[k];
+            if (v) atomicAdd(dst + k, v);
+        }
     }
 }
 
 #ifndef HPMC_SPHERE_WAVES_PER_EU
-#define HPMC_SPHERE_WAVES_PER_EU 3
+#define HPMC_SPHERE_WAVES_PER_EU 4
 #endif
 // F32: depletant tests in FP32 with the FP64 guard band (precision HPMC_FP32_GUARDED);
 // SHELL: depletants in the shell region
 template <bool F32, bool SHELL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F32 ? 2 : HPMC_SPHERE_WAVES_PER_EU, 8))) void
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F32 ? 3 : HPMC_SPHERE_WAVES_PER_EU, 8))) void
 phase_sphere_kernel(const Desc* __restrict__ D, int phase)
 {
     Params P = D[blockIdx.y].P;

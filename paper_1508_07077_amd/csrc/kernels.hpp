@@ -59,6 +59,7 @@ struct Params {
     int list_cap, geo_cap;
     int wave_lds;       // bytes per wave
     int off_own_pos, off_own_q, off_geo;
+    int off_cnt;        // spheres: the wave's counters (the two stage buffers come before it)
     // oriented shapes, per trial: stencil entries whose circumsphere meets the
     // proposed pose's (close list) and entries a depletant or CB trial can reach
     int close_cap, reach_cap, off_close, off_reach;
