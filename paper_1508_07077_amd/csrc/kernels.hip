@@ -68,7 +68,10 @@ struct NbOff {
 };
 __device__ inline NbOff nb_offset(int n)
 {
-    const int l = lane_id();
+    int l = lane_id();
+    // opaque to the optimiser: the offsets are recomputed where they are used
+    // (a few integer operations) instead of held in registers across loops
+    asm volatile("" : "+v"(l));
     NbOff o;
     if (n == 2) {
         o.on = l < 8;
@@ -417,6 +420,8 @@ struct TrialOut {
 // ---------------------------------------------------------------------------
 // grid, cells
 // ---------------------------------------------------------------------------
+__device__ inline void grid_setup(const Params& P, const Work& W);
+
 __global__ void grid_kernel(const Desc* __restrict__ D, int with_grid)
 {
     Params P = D[blockIdx.y].P;
@@ -428,21 +433,7 @@ __global__ void grid_kernel(const Desc* __restrict__ D, int with_grid)
         for (int i = 0; i < 8; ++i) W.perm[i] = i;
         return;
     }
-    Words a = draw(P, kNoCell, 0, kGrid, 0);
-    W.grid[0] = P.w * u01(a.w0);
-    W.grid[1] = P.w * u01(a.w1);
-    W.grid[2] = P.w * u01(a.w2);
-    Words b = draw(P, kNoCell, 0, kGrid, 1);
-    Words c = draw(P, kNoCell, 0, kGrid, 2);
-    uint32_t fy[7] = {b.w0, b.w1, b.w2, b.w3, c.w0, c.w1, c.w2};
-    int perm[8] = {0, 1, 2, 3, 4, 5, 6, 7};
-    for (int i = 7, f = 0; i >= 1; --i, ++f) {
-        int j = static_cast<int>(pick(fy[f], static_cast<uint32_t>(i + 1)));
-        int tmp = perm[i];
-        perm[i] = perm[j];
-        perm[j] = tmp;
-    }
-    for (int i = 0; i < 8; ++i) W.perm[i] = perm[i];
+    grid_setup(P, W);
 }
 
 __global__ void clear_counters_kernel(const Desc* __restrict__ D)
@@ -646,7 +637,7 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
     __syncthreads();
 
     const int lane = lane_id();
-    const int wv = threadIdx.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));  // wave-uniform
     unsigned char* wbase = smem + kTableLds + static_cast<size_t>(wv) * P.wave_lds;
     WaveCtx c;
     c.list = reinterpret_cast<int*>(wbase);
@@ -1121,7 +1112,7 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
     int* sG = reinterpret_cast<int*>(smem + kPoissonK * sizeof(double));
 
     const int lane = lane_id();
-    const int wv = threadIdx.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));  // wave-uniform
     unsigned char* wbase = smem + kTableLds + static_cast<size_t>(wv) * P.wave_lds;
     auto stage_buf = [&](int b) {
         unsigned char* q = wbase + static_cast<size_t>(b) * (P.off_cnt / 2);
@@ -1140,31 +1131,31 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
     const Mat3 Rnone{};
 
     // the chunk: lane k < P.chunk holds active cell gw * P.chunk + k
-    int Ck = -1, startk = 0, nck = 0, cxk = 0, cyk = 0, czk = 0;
+    int Ck = -1, startk = 0, nck = 0;
     {
         int a = gw * P.chunk + lane;
         if (lane < P.chunk && a < P.active_cells) {
             int ax = a % P.h, ay = (a / P.h) % P.h, az = a / (P.h * P.h);
-            cxk = 2 * ax + (colour & 1);
-            cyk = 2 * ay + ((colour >> 1) & 1);
-            czk = 2 * az + ((colour >> 2) & 1);
+            const int cxk = 2 * ax + (colour & 1);
+            const int cyk = 2 * ay + ((colour >> 1) & 1);
+            const int czk = 2 * az + ((colour >> 2) & 1);
             Ck = cxk + P.n * (cyk + P.n * czk);
             startk = W.cell_start[Ck];
             nck = W.cell_start[Ck + 1] - startk;
         }
     }
     unsigned long long todo = __ballot(nck > 0);
-    const NbOff nb = nb_offset(P.n);
     // ranges of the stencil of chunk cell k (k < 0: none)
     auto ranges_of = [&](int k, int& es, int& ec) {
+        const NbOff nb = nb_offset(P.n);
         if (k < 0) {
             stencil_ranges(P, W, nb, -1, 0, 0, 0, es, ec);
             return;
         }
-        stencil_ranges(P, W, nb, static_cast<int>(rdlane_u(static_cast<uint32_t>(Ck), k)),
-                       static_cast<int>(rdlane_u(static_cast<uint32_t>(cxk), k)),
-                       static_cast<int>(rdlane_u(static_cast<uint32_t>(cyk), k)),
-                       static_cast<int>(rdlane_u(static_cast<uint32_t>(czk), k)), es, ec);
+        // the cell's coordinates from its id (wave-uniform arithmetic, no registers held per lane)
+        const int C = static_cast<int>(rdlane_u(static_cast<uint32_t>(Ck), k));
+        const int cyz = C / P.n;
+        stencil_ranges(P, W, nb, C, C - P.n * cyz, cyz % P.n, cyz / P.n, es, ec);
     };
     // pipeline: ranges two cells ahead, records one cell ahead
     auto next_cell = [&](unsigned long long& m) -> int {
@@ -1438,7 +1429,7 @@ phase_sphere_kernel(const Desc* __restrict__ D, int phase)
     load_table(W, smem);
     __syncthreads();
     phase_sphere_body<F32, SHELL>(P, W, phase, static_cast<int>(blockIdx.x) * P.waves_per_block +
-                                                   static_cast<int>(threadIdx.x >> 6));
+                                                   __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6)));
 }
 
 // Small sphere boxes: one workgroup of kSmallWaves waves sweeps a whole
@@ -1454,15 +1445,19 @@ __device__ inline void grid_setup(const Params& P, const Work& W)
     W.grid[2] = P.w * u01(a.w2);
     Words b = draw(P, kNoCell, 0, kGrid, 1);
     Words c = draw(P, kNoCell, 0, kGrid, 2);
-    uint32_t fy[7] = {b.w0, b.w1, b.w2, b.w3, c.w0, c.w1, c.w2};
-    int perm[8] = {0, 1, 2, 3, 4, 5, 6, 7};
-    for (int i = 7, f = 0; i >= 1; --i, ++f) {
-        int j = static_cast<int>(pick(fy[f], static_cast<uint32_t>(i + 1)));
-        int tmp = perm[i];
-        perm[i] = perm[j];
-        perm[j] = tmp;
+    const uint32_t fy[7] = {b.w0, b.w1, b.w2, b.w3, c.w0, c.w1, c.w2};
+    // Fisher-Yates over the 8 colours; the permutation is packed four bits
+    // per entry into one register (entry i in bits 4i .. 4i + 3)
+    uint32_t perm = 0x76543210u;
+#pragma unroll
+    for (int i = 7; i >= 1; --i) {
+        const uint32_t j = pick(fy[7 - i], static_cast<uint32_t>(i + 1));
+        const uint32_t si = 4u * static_cast<uint32_t>(i), sj = 4u * j;
+        const uint32_t pi = (perm >> si) & 15u, pj = (perm >> sj) & 15u;
+        perm &= ~((15u << si) | (15u << sj));
+        perm |= (pj << si) | (pi << sj);
     }
-    for (int i = 0; i < 8; ++i) W.perm[i] = perm[i];
+    for (int i = 0; i < 8; ++i) W.perm[i] = static_cast<int>((perm >> (4 * i)) & 15u);
 }
 
 template <bool F32, bool SHELL>
