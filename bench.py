@@ -56,9 +56,9 @@ def shell_ops_per_check(R0: float, r_i: float) -> float:
 # work.  HBM bytes per launch from two rocprofv3 passes (FETCH_SIZE,
 # WRITE_SIZE) scaled by the same counters over a plain 256 MiB device copy.
 # Both hold only for the kernel sources with this digest.
-PROFILED_KERNEL_DIGEST = "8c36c15aa59861c4"
-CALIBRATED_OPS_PER_CHECK = 263.35
-PROFILED_TRAFFIC_BYTES = {"ball": 109905797, "shell": 110428385}
+PROFILED_KERNEL_DIGEST = "b0aa16ac79b0454d"
+CALIBRATED_OPS_PER_CHECK = 230.78
+PROFILED_TRAFFIC_BYTES = {"ball": 98971446, "shell": 99450709}
 
 
 def kernel_digest() -> str:
