@@ -114,6 +114,21 @@ __device__ inline void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (block b runs on XCD
+// b mod 8, each XCD with its own L2).  This hands the XCDs runs of kXcdRun
+// consecutive logical blocks in turn, so neighbouring chunks of cells, whose
+// stencils overlap, are read through the same L2 while every XCD still gets
+// work from all over the box.  A bijection on [0, nb): the blocks past the
+// last whole round of runs keep their index.
+constexpr int kXcdRun = 16;
+__device__ inline int xcd_block(int b, int nb)
+{
+    const int main = nb / (8 * kXcdRun) * (8 * kXcdRun);
+    if (b >= main) return b;
+    const int x = b & 7, i = b >> 3;
+    return ((i / kXcdRun) * 8 + x) * kXcdRun + i % kXcdRun;
+}
+
 __device__ inline int wave_excl_scan(int v, int& total)
 {
     int x = v;
@@ -1428,8 +1443,13 @@ phase_sphere_kernel(const Desc* __restrict__ D, int phase)
     extern __shared__ __align__(16) unsigned char smem[];
     load_table(W, smem);
     __syncthreads();
-    phase_sphere_body<F32, SHELL>(P, W, phase, static_cast<int>(blockIdx.x) * P.waves_per_block +
-                                                   __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6)));
+    // one box: XCD-aware chunk order; a batch keeps the dispatch order, since
+    // its small replicas have work only in their first blocks
+    const int b = gridDim.y == 1 ? xcd_block(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x))
+                                 : static_cast<int>(blockIdx.x);
+    phase_sphere_body<F32, SHELL>(P, W, phase,
+                                  b * P.waves_per_block +
+                                      __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6)));
 }
 
 // Small sphere boxes: one workgroup of kSmallWaves waves sweeps a whole
