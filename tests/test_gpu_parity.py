@@ -53,7 +53,8 @@ def test_c3_shaped_box_cb():
     assert tot["depletants_drawn"] > 300 * tot["trials"] * 0.5
 
 
-@pytest.mark.parametrize("case", ["single", "two_in_n2_box", "dilute", "n_select3", "zero_fugacity", "big_step"])
+@pytest.mark.parametrize("case", ["single", "two_in_n2_box", "dilute", "n_select3", "zero_fugacity", "big_step",
+                                  "dense_two_cell"])
 def test_edge_cases(case):
     if case == "single":
         sp = wl.StatePoint(wl.SPHERE, (1.0,), 1, 0.01, 0.25, 0.10, d_trans=0.2, seed=3)
@@ -65,8 +66,11 @@ def test_edge_cases(case):
         sp = wl.StatePoint(wl.SPHERE, (1.0,), 64, 0.20, 0.25, 0.10, d_trans=0.1, seed=6)
     elif case == "zero_fugacity":
         sp = wl.StatePoint(wl.SPHERE, (1.0,), 300, 0.35, 0.25, 0.0, d_trans=0.1, seed=7)
-    else:
+    elif case == "big_step":
         sp = wl.StatePoint(wl.SPHERE, (1.0,), 100, 0.10, 0.5, 0.2, n_trial=3, d_trans=0.8, seed=8)
+    else:
+        # 90 spheres in a two-cell box: a stencil of 90 entries, past the 64 staged in LDS
+        sp = wl.StatePoint(wl.SPHERE, (1.0,), 90, 0.45, 0.25, 0.2, n_trial=2, d_trans=0.1, seed=9)
     pos, _ = sp.initial_state()
     g, o = make_pair(sp, pos)
     if case == "n_select3":
@@ -107,6 +111,20 @@ def test_discoids():
     tot, div = compare_sweeps(g, o, 6, allow_near=True)
     assert div <= 1
     assert tot["accepts"] > 0
+
+
+@pytest.mark.parametrize("n, phi", [(128, 0.45), (600, 0.40)], ids=["two_cell_box", "four_cell_box"])
+def test_dense_discoids(n, phi):
+    """dense swept disks: stencils of more than 64 entries (the per-trial close
+    and reach lists) and, in the two-cell box, more than the 96 entries the
+    geometry cache holds (the rest read from the records)"""
+    sp = wl.StatePoint(wl.DISCOID, (0.5, 0.1), n, phi, 0.2, 0.40, n_trial=1, d_trans=0.02, a_rot=0.02,
+                       p_rot=0.5, seed=14)
+    pos, quat = _melt(sp, 6)
+    g, o = make_pair(sp, pos, quat)
+    tot, div = compare_sweeps(g, o, 4, allow_near=True)
+    assert div <= 1
+    assert tot["accepts"] > 0 and tot["rej_overlap"] > 0 and tot["depletants_drawn"] > 0
 
 
 def test_overlapping_state_rejected():
