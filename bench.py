@@ -56,9 +56,9 @@ def shell_ops_per_check(R0: float, r_i: float) -> float:
 # work.  HBM bytes per launch from two rocprofv3 passes (FETCH_SIZE,
 # WRITE_SIZE) scaled by the same counters over a plain 256 MiB device copy.
 # Both hold only for the kernel sources with this digest.
-PROFILED_KERNEL_DIGEST = "b0aa16ac79b0454d"
+PROFILED_KERNEL_DIGEST = "a2237bce87070ad8"
 CALIBRATED_OPS_PER_CHECK = 230.78
-PROFILED_TRAFFIC_BYTES = {"ball": 98971446, "shell": 99450709}
+PROFILED_TRAFFIC_BYTES = {"ball": 70859938, "shell": 70970774}
 
 
 def kernel_digest() -> str:
