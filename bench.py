@@ -89,6 +89,8 @@ def parse():
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="skip the launch-shape autotuner (default: tune before timing)")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="c5: length of the arrival trace")
+    ap.add_argument("--capacity-requests", type=int, default=60,
+                    help="c5: requests of the trace served all at once, batched and one at a time")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (scales the HBM byte counters)")
     return ap.parse_args()
@@ -137,7 +139,7 @@ def cpu_baseline(sp_factory, n_sample: int, seconds: float):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build runs on a single MI355X)",
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the library runs on one MI355X)",
               file=sys.stderr)
         sys.exit(2)
     import numpy as np
@@ -453,11 +455,23 @@ def bench_c4(args):
         c = {k: sum(x[k] for x in cs) for k in cs[0]}
         tot = c if tot is None else {k: tot[k] + c[k] for k in tot}
     dt = time.perf_counter() - t0
+    # the same replicas swept one at a time (each handle's own launches), for comparison
+    for x in sims:
+        x.sweep(1, counters=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(2):
+        for x in sims:
+            x.sweep(1, counters=False)
+    torch.cuda.synchronize()
+    dt1 = time.perf_counter() - t1
+    alone = {"moves_per_s": 2 * sum(x.n for x in sims) / dt1, "ms_per_sweep": dt1 * 1e3 / 2,
+             "note": "the same replicas, each swept alone in turn (2 sweeps)"}
     return _line(tot["trials"] / dt, tot, dt, args.steps, 3,
                  f"256 swept-disk replicas, N={sum(s.n for s in sps)} in total (128..8192 each), "
                  "phi_c U[0.05,0.45], eta_r U[0,0.5], q=0.2, one launch per kernel for all replicas",
                  {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                  "replicas": len(sps), "launch_tuning": tuning})
+                  "replicas": len(sps), "launch_tuning": tuning, "one_at_a_time": alone})
 
 
 def bench_c5(args):
@@ -480,6 +494,19 @@ def bench_c5(args):
     dt = time.perf_counter() - t0
     summ = serve.latency_summary(done)
     errors = sum(1 for r in done if "error" in r.result)
+    # capacity with every request of a sample available at once: continuous
+    # batching against one request at a time, same requests and work
+    sample = specs[: args.capacity_requests]
+    cap = {}
+    for label, max_active in (("batched", 256), ("one_at_a_time", 1)):
+        rq = [serve.Request(sp, sp.extra["sweeps"], 0.0, rid=i) for i, sp in enumerate(sample)]
+        s2 = serve.Server(sweeps_per_tick=1, max_active=max_active)
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        s2.run(rq, realtime=False)
+        torch.cuda.synchronize()
+        cap[label + "_moves_per_s"] = s2.moves / (time.perf_counter() - tc)
+    cap["requests"] = len(sample)
     return {
         "metric": "colloid trial moves/s + depletant overlap checks/s (1 GPU); p50/p99 latency",
         "value": srv.moves / dt,
@@ -501,6 +528,7 @@ def bench_c5(args):
         "requests": summ["requests"],
         "failed_requests": errors,
         "latency_note": "per request, arrival to observables returned",
+        "capacity": cap,
     }
 
 
