@@ -141,6 +141,15 @@ __device__ inline int wave_excl_scan(int v, int& total)
     return x - v;
 }
 
+// sum of v over lanes first .. first + n - 1 (n wave-uniform and small):
+// scalar reads of the lanes instead of a cross-lane reduction tree
+__device__ inline int lanes_sum(int v, int first, int n)
+{
+    int s = 0;
+    for (int i = 0; i < n; ++i) s += __builtin_amdgcn_readlane(v, first + i);
+    return s;
+}
+
 __device__ inline int wave_sum(int v)
 {
 #pragma unroll
@@ -874,7 +883,8 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
                             kc += poisson_guided(sF, sG, u52(pw.w0, pw.w1));
                         }
                     }
-                    const uint32_t Np = static_cast<uint32_t>(wave_sum(kc));
+                    // chunk counts sit in lanes 3 .. 3 + n_chunks - 1 (more chunks: in every lane)
+                    const uint32_t Np = static_cast<uint32_t>(P.n_chunks <= 8 ? lanes_sum(kc, 3, P.n_chunks) : wave_sum(kc));
                     o.n_dep = Np;
                     const double au = u52(rdlane_u(w.w0, 2), rdlane_u(w.w1, 2));
                     const Vec3 Dold = v3(mi(P, pj.x - xn.x), mi(P, pj.y - xn.y), mi(P, pj.z - xn.z));
@@ -1270,7 +1280,9 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
                                 kcnt += poisson_guided(sF, sG, u52(pw.w0, pw.w1));
                             }
                         }
-                        const uint32_t Np = static_cast<uint32_t>(wave_sum(kcnt));
+                        // chunk counts sit in lanes 3 .. 3 + n_chunks - 1 (more chunks: in every lane)
+                        const uint32_t Np = static_cast<uint32_t>(P.n_chunks <= 8 ? lanes_sum(kcnt, 3, P.n_chunks)
+                                                                                  : wave_sum(kcnt));
                         o.n_dep = Np;
                         const double au = u52(rdlane_u(w.w0, 2), rdlane_u(w.w1, 2));
                         const Vec3 Dold = v3(mi(P, pj.x - xn.x), mi(P, pj.y - xn.y), mi(P, pj.z - xn.z));
