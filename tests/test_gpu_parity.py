@@ -54,7 +54,7 @@ def test_c3_shaped_box_cb():
 
 
 @pytest.mark.parametrize("case", ["single", "two_in_n2_box", "dilute", "n_select3", "zero_fugacity", "big_step",
-                                  "dense_two_cell"])
+                                  "dense_two_cell", "many_chunks", "most_chunks"])
 def test_edge_cases(case):
     if case == "single":
         sp = wl.StatePoint(wl.SPHERE, (1.0,), 1, 0.01, 0.25, 0.10, d_trans=0.2, seed=3)
@@ -68,9 +68,15 @@ def test_edge_cases(case):
         sp = wl.StatePoint(wl.SPHERE, (1.0,), 300, 0.35, 0.25, 0.0, d_trans=0.1, seed=7)
     elif case == "big_step":
         sp = wl.StatePoint(wl.SPHERE, (1.0,), 100, 0.10, 0.5, 0.2, n_trial=3, d_trans=0.8, seed=8)
-    else:
+    elif case == "dense_two_cell":
         # 90 spheres in a two-cell box: a stencil of 90 entries, past the 64 staged in LDS
         sp = wl.StatePoint(wl.SPHERE, (1.0,), 90, 0.45, 0.25, 0.2, n_trial=2, d_trans=0.1, seed=9)
+    elif case == "many_chunks":
+        # 4,630 depletants per move: 19 Poisson chunks (the cross-lane total)
+        sp = wl.StatePoint(wl.SPHERE, (1.0,), 27, 0.10, 0.05, 0.5, d_trans=0.01, seed=10)
+    else:
+        # 50,000 depletants per move: 196 chunks, past the first pass over the lanes
+        sp = wl.StatePoint(wl.SPHERE, (1.0,), 27, 0.10, 0.022, 0.5, n_trial=1, d_trans=0.002, seed=10)
     pos, _ = sp.initial_state()
     g, o = make_pair(sp, pos)
     if case == "n_select3":
@@ -92,6 +98,18 @@ def test_hemispheres():
     tot, div = compare_sweeps(g, o, 8, allow_near=True)
     assert div <= 1
     assert tot["rej_overlap"] > 0 and tot["rej_depletant"] > 0 and tot["accepts"] > 0
+
+
+def test_hemispheres_many_chunks():
+    """20,000 depletants per move: 80 Poisson chunks, past the oriented kernel's
+    first pass over the lanes"""
+    sp = wl.StatePoint(wl.HEMISPHERE, (1.0,), 40, 0.10, 0.03, 0.5, n_trial=0, d_trans=0.01, a_rot=0.01,
+                       p_rot=0.5, seed=15)
+    pos, quat = sp.initial_state()
+    g, o = make_pair(sp, pos, quat)
+    tot, div = compare_sweeps(g, o, 2, allow_near=True)
+    assert div <= 1
+    assert tot["depletants_drawn"] > 15000 * tot["trials"] * 0.5
 
 
 def test_hemispheres_cb():
