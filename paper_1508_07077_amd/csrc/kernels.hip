@@ -1578,7 +1578,7 @@ __global__ __launch_bounds__(64 * kSmallWaves) void sweep_small_kernel(const Des
 
 // F32: depletant predicates in FP32 with the FP64 guard band
 template <int KIND, bool F32>
-__global__ __launch_bounds__(256) void phase_oriented_kernel(const Desc* __restrict__ D, int phase)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F32 ? 2 : 1, 8))) void phase_oriented_kernel(const Desc* __restrict__ D, int phase)
 {
     Params P = D[blockIdx.y].P;
     const Work W = D[blockIdx.y].W;

@@ -170,6 +170,36 @@ def test_sweep_before_state_is_an_error():
     assert e.value.code == -5
 
 
+def test_empty_and_zero_inputs():
+    """no particles is an invalid argument; zero sweeps (alone and batched)
+    leave the state, the sweep index and the counters untouched"""
+    import paper_1508_07077_amd as hp
+
+    with pytest.raises(hp.HpmcError) as e:
+        hp.Sim(0, 6.9459, 1)
+    assert e.value.code == -1
+    sp = wl.c1_spheres_small(1)
+    pos, _ = sp.initial_state()
+    sims = []
+    for _ in range(2):
+        g = hp.Sim(sp.n, sp.L, sp.seed)
+        g.set_shape(hp.SPHERE, sp.params)
+        g.set_fugacity(sp.z_p, sp.d_dep, sp.n_trial)
+        g.set_moves(sp.d_trans)
+        g.set_state(pos)
+        sims.append(g)
+    c = sims[0].sweep(0)
+    assert all(v == 0 for k, v in c.items() if not k.endswith("_ms"))
+    for cb in hp.Batch(sims).sweep(0):
+        assert cb["trials"] == 0
+    for g in sims:
+        p2, _, s2 = g.get_state()
+        assert s2 == 0 and np.array_equal(p2, pos)
+    with pytest.raises(hp.HpmcError) as e:
+        sims[0].sweep(-1)
+    assert e.value.code == -1
+
+
 def test_full_size_c3_sampled_cells():
     """N = 1,048,576 spheres at the benchmark's settings: one traced GPU sweep
     from the generator's lattice; for sampled cells (one per phase) the oracle
