@@ -1446,7 +1446,7 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
 // F32: depletant tests in FP32 with the FP64 guard band (precision HPMC_FP32_GUARDED);
 // SHELL: depletants in the shell region
 template <bool F32, bool SHELL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F32 ? 3 : HPMC_SPHERE_WAVES_PER_EU, 8))) void
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HPMC_SPHERE_WAVES_PER_EU, 8))) void
 phase_sphere_kernel(const Desc* __restrict__ D, int phase)
 {
     Params P = D[blockIdx.y].P;
