@@ -56,9 +56,9 @@ def shell_ops_per_check(R0: float, r_i: float) -> float:
 # work.  HBM bytes per launch from two rocprofv3 passes (FETCH_SIZE,
 # WRITE_SIZE) scaled by the same counters over a plain 256 MiB device copy.
 # Both hold only for the kernel sources with this digest.
-PROFILED_KERNEL_DIGEST = "8712e229ba79188e"
+PROFILED_KERNEL_DIGEST = "6b4316646c2228c3"
 CALIBRATED_OPS_PER_CHECK = 228.60
-PROFILED_TRAFFIC_BYTES = {"ball": 74828350, "shell": 74945023}
+PROFILED_TRAFFIC_BYTES = {"ball": 70864838, "shell": 70978716}
 
 
 def kernel_digest() -> str:
