@@ -150,18 +150,26 @@ struct PairResult {
 
 // Minkowski portal refinement on the difference B - A (B at offset d with
 // rotation RB, A at the origin with rotation RA).  The origin lies inside the
-// difference iff the shapes overlap.  Interior seed: difference of the
-// shapes' interior points (hemisphere centroid (0,0,3a/8), disk centre).
+// difference iff the shapes overlap.  It runs in A's body frame, where A's
+// support needs no rotation and B sits at RA^T d with rotation RA^T RB.
+// Interior seed: difference of the shapes' interior points (hemisphere
+// centroid (0,0,3a/8), disk centre).
 __host__ __device__ inline PairResult mpr_overlap(const Shape& S, Vec3 d, const Mat3& RA, const Mat3& RB)
 {
     const double tol = 1e-13;
     PairResult res{false, false};
+    const Vec3 dA = to_body(RA, d);
+    Mat3 RAB;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            RAB.m[3 * i + j] = (RA.m[i] * RB.m[j] + RA.m[3 + i] * RB.m[3 + j]) + RA.m[6 + i] * RB.m[6 + j];
     Vec3 cin = v3(0.0, 0.0, S.kind == kHemisphere ? 0.375 * S.a : 0.0);
-    Vec3 zero = v3(0.0, 0.0, 0.0);
-    Vec3 v0 = (d + to_world(RB, cin)) - to_world(RA, cin);
+    Vec3 v0 = (dA + to_world(RAB, cin)) - cin;
     if (dot(v0, v0) < 1e-30) v0 = v3(1e-12, 0.0, 0.0);
     // support of B - A in direction n
-#define HPMC_SUP(n) (support_world(S, RB, d, (n)) - support_world(S, RA, zero, neg(n)))
+#define HPMC_SUP(n) (support_world(S, RAB, dA, (n)) - support_body(S, neg(n)))
     Vec3 n = neg(v0);
     Vec3 v1 = HPMC_SUP(n);
     if (dot(v1, n) <= 0.0) return res;
