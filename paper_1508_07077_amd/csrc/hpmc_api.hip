@@ -284,9 +284,9 @@ Params make_params(const hpmc_sim* s)
     if (!s->S.oriented) {
         // spheres: two stage buffers, each the stencil list + staged records (x, y) and (z, index)
         size_t o = align256(static_cast<size_t>(list_cap) * 4);
-        P.off_own_pos = static_cast<int>(o);
+        P.off_rec_a = static_cast<int>(o);
         o = align256(o + 64 * 16);
-        P.off_own_q = static_cast<int>(o);
+        P.off_rec_b = static_cast<int>(o);
         o = align256(o + 64 * 16);
         P.off_geo = 0;
         P.off_cnt = static_cast<int>(2 * o);  // after the two stage buffers: the wave's counters

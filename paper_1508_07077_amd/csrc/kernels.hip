@@ -1141,8 +1141,8 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
     unsigned char* wbase = smem + kTableLds + static_cast<size_t>(wv) * P.wave_lds;
     auto stage_buf = [&](int b) {
         unsigned char* q = wbase + static_cast<size_t>(b) * (P.off_cnt / 2);
-        return SphereStage{reinterpret_cast<int*>(q), reinterpret_cast<double*>(q + P.off_own_pos),
-                           reinterpret_cast<double*>(q + P.off_own_q)};
+        return SphereStage{reinterpret_cast<int*>(q), reinterpret_cast<double*>(q + P.off_rec_a),
+                           reinterpret_cast<double*>(q + P.off_rec_b)};
     };
 
     // the wave's counters live in its LDS (uniform values, no registers); lane

@@ -58,12 +58,13 @@ struct Params {
     // per-wave LDS layout of the phase kernel
     int list_cap, geo_cap;
     int wave_lds;       // bytes per wave
-    int off_own_pos, off_own_q, off_geo;
+    int off_rec_a, off_rec_b;  // spheres: staged (x, y) and (z, index) pairs within a stage buffer
+    int off_geo;        // oriented shapes: the geometry cache
     int off_cnt;        // spheres: the wave's counters (the two stage buffers come before it)
     // oriented shapes, per trial: stencil entries whose circumsphere meets the
     // proposed pose's (close list) and entries a depletant or CB trial can reach
     int close_cap, reach_cap, off_close, off_reach;
-    double reach_sq;    // (R0 + r_circ + r_dep + sqrt(3) d_trans)^2 plus a margin
+    double reach_sq;    // (R0 + r_circ + r_dep + sqrt(3) d_trans)^2 plus a margin (spheres: the CB reach mask)
     int waves_per_block;
     int chunk;          // spheres: active cells per wave (1..64)
     int active_cells;   // h^3
