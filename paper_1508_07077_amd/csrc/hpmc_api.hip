@@ -274,7 +274,7 @@ Params make_params(const hpmc_sim* s)
     double rc2 = 2.0 * s->S.rcirc;
     int64_t list_cap = (s->n == 2) ? s->N : packing_bound(s, 3.0 * s->w + rc2);
     int gs = s->S.oriented ? 12 : 3;
-    int64_t geo_cap = s->S.oriented ? std::min<int64_t>(list_cap, 96) : std::min<int64_t>(list_cap, 512);
+    int64_t geo_cap = s->S.oriented ? std::min<int64_t>(list_cap, 64) : std::min<int64_t>(list_cap, 512);
     P.list_cap = static_cast<int>(list_cap);
     P.geo_cap = static_cast<int>(geo_cap);
     // A depletant point of B(x', R0) or a CB trial point of B(x, R0) can only

@@ -134,8 +134,8 @@ def test_discoids():
 @pytest.mark.parametrize("n, phi", [(128, 0.45), (600, 0.40)], ids=["two_cell_box", "four_cell_box"])
 def test_dense_discoids(n, phi):
     """dense swept disks: stencils of more than 64 entries (the per-trial close
-    and reach lists) and, in the two-cell box, more than the 96 entries the
-    geometry cache holds (the rest read from the records)"""
+    and reach lists) and more than the 64 entries the geometry cache holds
+    (the rest read from the records)"""
     sp = wl.StatePoint(wl.DISCOID, (0.5, 0.1), n, phi, 0.2, 0.40, n_trial=1, d_trans=0.02, a_rot=0.02,
                        p_rot=0.5, seed=14)
     pos, quat = _melt(sp, 6)
