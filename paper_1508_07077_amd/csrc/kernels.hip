@@ -1299,8 +1299,11 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
                             uint32_t k1 = k0 + (acc0 ? 1u : 0u);
                             // ignored by the old pose (every ball point overlaps the new pose)
                             bool v0 = acc0 && k0 < Np, v1 = acc1 && k1 < Np;
-                            v0 = v0 && !sphere_in<F32>(P, e0, Dold, v0, fallbacks);
-                            v1 = v1 && !sphere_in<F32>(P, e1, Dold, v1, fallbacks);
+                            // evaluated in every lane (no branch; a lane's value counts only where valid)
+                            const bool in0 = sphere_in<F32>(P, e0, Dold, v0, fallbacks);
+                            const bool in1 = sphere_in<F32>(P, e1, Dold, v1, fallbacks);
+                            v0 = v0 && !in0;
+                            v1 = v1 && !in1;
                             unsigned long long r0 = __ballot(v0), r1 = __ballot(v1);
                             while ((r0 | r1) && !done) {
                                 int l0 = r0 ? ffs64(r0) : 64, l1 = r1 ? ffs64(r1) : 64;
