@@ -56,9 +56,9 @@ def shell_ops_per_check(R0: float, r_i: float) -> float:
 # work.  HBM bytes per launch from two rocprofv3 passes (FETCH_SIZE,
 # WRITE_SIZE) scaled by the same counters over a plain 256 MiB device copy.
 # Both hold only for the kernel sources with this digest.
-PROFILED_KERNEL_DIGEST = "a07789f2d065fdc5"
+PROFILED_KERNEL_DIGEST = "aad0ac7b56415011"
 CALIBRATED_OPS_PER_CHECK = 228.60
-PROFILED_TRAFFIC_BYTES = {"ball": 70858338, "shell": 70972194}
+PROFILED_TRAFFIC_BYTES = {"ball": 70861035, "shell": 70972771}
 
 
 def kernel_digest() -> str:
