@@ -316,7 +316,8 @@ __device__ inline float core_dist32(const Shape& S, float px, float py, float pz
 // (the FP32 error of the distance is below 1e-6 for |v| < 4), FP64 inside it
 // (counted in fb).
 template <int KIND, bool F32>
-__device__ inline bool dep_ov_g(const Params& P, Vec3 v, const Mat3& R, const Mat3f& Rf, unsigned& fb)
+__device__ inline bool dep_ov_g(const Params& P, Vec3 v, const Mat3& R, const Mat3f& Rf, unsigned& fb,
+                                bool counted = true)
 {
     if constexpr (!F32) {
         return dep_ov<KIND>(P.S, v, R);
@@ -328,7 +329,7 @@ __device__ inline bool dep_ov_g(const Params& P, Vec3 v, const Mat3& R, const Ma
         const float d = core_dist32<KIND>(P.S, px, py, pz);
         if (d < P.g_lo) return true;
         if (d > P.g_hi) return false;
-        ++fb;
+        if (counted) ++fb;
         return dep_ov<KIND>(P.S, v, R);
     }
 }
@@ -902,13 +903,16 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
                         uint32_t k1 = k0 + (acc0 ? 1u : 0u);
                         bool v0 = acc0 && k0 < Np, v1 = acc1 && k1 < Np;
                         // irrelevant (misses M') or ignored by the old pose
-                        if (v0) {
-                            if constexpr (ORI) v0 = dep_ov_g<KIND, F32>(P, e0, Rn, Rn32, fb);
-                            if (v0) v0 = !dep_ov_g<KIND, F32>(P, e0 - Dold, Ro, Ro32, fb);
-                        }
-                        if (v1) {
-                            if constexpr (ORI) v1 = dep_ov_g<KIND, F32>(P, e1, Rn, Rn32, fb);
-                            if (v1) v1 = !dep_ov_g<KIND, F32>(P, e1 - Dold, Ro, Ro32, fb);
+                        {
+                            // evaluated in every lane (no branch); a fallback is counted only
+                            // where the test decides: valid candidate, and for the old pose
+                            // one that overlaps the new pose
+                            const bool n0 = dep_ov_g<KIND, F32>(P, e0, Rn, Rn32, fb, v0);
+                            const bool n1 = dep_ov_g<KIND, F32>(P, e1, Rn, Rn32, fb, v1);
+                            const bool o0 = dep_ov_g<KIND, F32>(P, e0 - Dold, Ro, Ro32, fb, v0 && n0);
+                            const bool o1 = dep_ov_g<KIND, F32>(P, e1 - Dold, Ro, Ro32, fb, v1 && n1);
+                            v0 = v0 && n0 && !o0;
+                            v1 = v1 && n1 && !o1;
                         }
                         unsigned long long r0 = __ballot(v0), r1 = __ballot(v1);
                         // survivors in ascending depletant index: lane order, candidate 0 before 1
