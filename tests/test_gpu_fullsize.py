@@ -1,7 +1,7 @@
 """Parity at the benchmark's full sizes, in the launch configurations the
-benchmark times: 16,384 hemispheres swept by one handle, and the 256
-swept-disk replicas swept together in shared launches, each against the
-oracle run on the same inputs.  Trials decided within 1e-9 of a colloid
+benchmark times: a whole sweep of the 1,048,576 spheres, 16,384 hemispheres
+swept by one handle, and the 256 swept-disk replicas swept together in shared
+launches, each against the oracle run on the same inputs.  Trials decided within 1e-9 of a colloid
 contact by either side's own convex test (MPR on the GPU, GJK in the oracle)
 may differ; every other decision, count and coordinate is bit-exact."""
 import numpy as np
@@ -11,6 +11,17 @@ from paper_1508_07077_amd import workloads as wl
 from parity_util import compare_sweeps, make_pair
 
 pytestmark = pytest.mark.gpu
+
+
+def test_full_size_spheres_whole_sweep():
+    """the 1,048,576-sphere workload: one whole sweep, all 1,048,576 trials
+    compared record by record (sphere tests are exact: no tolerance)"""
+    sp = wl.c3_spheres_large()
+    pos, _ = sp.initial_state()
+    g, o = make_pair(sp, pos)
+    tot, div = compare_sweeps(g, o, 1)
+    assert div == 0
+    assert tot["trials"] == sp.n and tot["cb_trials"] > 0
 
 
 @pytest.mark.parametrize("eta_r", [0.1, 0.4])
