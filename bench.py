@@ -76,7 +76,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--melt", type=int, default=20, help="untimed zero-fugacity sweeps from the lattice")
+    ap.add_argument("--melt", type=int, default=200, help="untimed zero-fugacity sweeps from the lattice")
     ap.add_argument("--n", type=int, default=1048576)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle CPU-baseline budget (0 disables)")
     ap.add_argument("--cpu-n", type=int, default=40000)
@@ -91,6 +91,12 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="c5: length of the arrival trace")
     ap.add_argument("--capacity-requests", type=int, default=60,
                     help="c5: requests of the trace served all at once, batched and one at a time")
+    ap.add_argument("--eta", default="0.1,0.2,0.3,0.4",
+                    help="c2: comma-separated reservoir packing fractions eta_r to run")
+    ap.add_argument("--no-fp32", dest="fp32", action="store_false",
+                    help="c2, c3: skip the FP32-guarded companion run")
+    ap.add_argument("--no-alone", dest="alone", action="store_false",
+                    help="c4: skip the one-replica-at-a-time comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (scales the HBM byte counters)")
     return ap.parse_args()
@@ -206,24 +212,9 @@ def main():
         "depletants_per_move": tot2["depletants_drawn"] / tot2["trials"],
     }
     # FP32 geometry with the FP64 guard band, same state point and region as the headline
-    s32 = hp.Sim(sp.n, sp.L, sp.seed, precision=hp.FP32_GUARDED)
-    s32.set_shape(hp.SPHERE, sp.params)
-    s32.set_fugacity(sp.z_p, sp.d_dep, sp.n_trial)
-    s32.set_moves(sp.d_trans)
-    s32.set_insertion(region)
-    s32.set_state(sim.pos.clone())
-    tot3, lat3, phase3, dt3 = _timed_sweeps(torch, s32, args.steps, args.warmup)
-    fp32 = {
-        "insertion_region": args.v0,
-        "moves_per_s": tot3["trials"] / dt3,
-        "depletant_checks_per_s": tot3["depletants_resolved"] / dt3,
-        "ms_per_step": dt3 * 1e3 / args.steps,
-        "avg_launch_ms": phase3 / launches,
-        "fp64_fallbacks": tot3["fp64_fallbacks"],
-        "fp64_fallbacks_per_depletant": tot3["fp64_fallbacks"] / max(tot3["depletants_drawn"], 1),
-        "note": "FP32 depletant tests with a 1e-5 sigma FP64 guard band; decisions equal to FP64",
-    }
-    s32.close()
+    fp32 = None
+    if args.fp32:
+        fp32 = _fp32_companion(hp, torch, sp, sim, region, args, launches)
     line = {
         "metric": "colloid trial moves/s + depletant overlap checks/s (1 GPU); p50/p99 latency",
         "value": moves,
@@ -278,6 +269,29 @@ def main():
     print(json.dumps(line), flush=True)
 
 
+def _fp32_companion(hp, torch, sp, sim, region, args, launches):
+    """the headline state point with FP32 depletant tests and the FP64 guard band"""
+    s32 = hp.Sim(sp.n, sp.L, sp.seed, precision=hp.FP32_GUARDED)
+    s32.set_shape(hp.SPHERE, sp.params)
+    s32.set_fugacity(sp.z_p, sp.d_dep, sp.n_trial)
+    s32.set_moves(sp.d_trans)
+    s32.set_insertion(region)
+    s32.set_state(sim.pos.clone())
+    tot3, lat3, phase3, dt3 = _timed_sweeps(torch, s32, args.steps, args.warmup)
+    fp32 = {
+        "insertion_region": args.v0,
+        "moves_per_s": tot3["trials"] / dt3,
+        "depletant_checks_per_s": tot3["depletants_resolved"] / dt3,
+        "ms_per_step": dt3 * 1e3 / args.steps,
+        "avg_launch_ms": phase3 / launches,
+        "fp64_fallbacks": tot3["fp64_fallbacks"],
+        "fp64_fallbacks_per_depletant": tot3["fp64_fallbacks"] / max(tot3["depletants_drawn"], 1),
+        "note": "FP32 depletant tests with a 1e-5 sigma FP64 guard band; decisions equal to FP64",
+    }
+    s32.close()
+    return fp32
+
+
 def _timed_sweeps(torch, sim, steps, warmup):
     """warmup untimed sweeps, then `steps` timed sweeps of one step each:
     (summed counters, per-step latencies in ms, summed phase-kernel ms, seconds)"""
@@ -298,19 +312,30 @@ def _timed_sweeps(torch, sim, steps, warmup):
     return tot, lat, phase_ms, time.perf_counter() - t0
 
 
-def _make(hp, sp, melt=20):
+def _prepare(hp, sp):
+    """a handle on the lattice start, set up for the untimed zero-fugacity melt"""
     pos, quat = sp.initial_state()
     sim = hp.Sim(sp.n, sp.L, sp.seed, sp.replica_id)
     sim.set_shape(sp.kind, sp.params)
     sim.set_fugacity(0.0, sp.d_dep, 0)
     sim.set_moves(0.1, 0.1 if sp.kind != 0 else 0.0, sp.p_rot)
     sim.set_state(pos, quat)
-    if melt:
-        sim.sweep(melt, counters=False)
+    return sim
+
+
+def _finish(sim, sp):
+    """after the melt: the state point's depletants and step sizes"""
     sim.set_fugacity(sp.z_p, sp.d_dep, sp.n_trial)
     sim.set_moves(sp.d_trans, sp.a_rot, sp.p_rot)
     sim.ensure_workspace()
     return sim
+
+
+def _make(hp, sp, melt=20):
+    sim = _prepare(hp, sp)
+    if melt:
+        sim.sweep(melt, counters=False)
+    return _finish(sim, sp)
 
 
 def _line(metric_value, tot, dt, steps, warmup, workload, extra):
@@ -380,7 +405,7 @@ def bench_c2(args):
     moves = checks = secs = 0.0
     lat = []
     fp32 = {}
-    for eta in (0.1, 0.2, 0.3, 0.4):
+    for eta in [float(x) for x in args.eta.split(",")]:
         sp = wl.c2_hemispheres(eta)
         sim = _make(hp, sp)
         tuning = sim.autotune(sweeps=2) if args.autotune else None
@@ -402,6 +427,8 @@ def bench_c2(args):
         moves += tot["trials"]
         checks += tot["depletants_resolved"]
         secs += dt
+        if not args.fp32:
+            continue
         # the same state point with FP32 depletant predicates and the FP64 guard band
         s32 = hp.Sim(sp.n, sp.L, sp.seed, sp.replica_id, precision=hp.FP32_GUARDED)
         s32.set_shape(sp.kind, sp.params)
@@ -433,7 +460,9 @@ def bench_c4(args):
     from paper_1508_07077_amd import workloads as wl
 
     sps = wl.c4_discoid_replicas()
-    sims = [_make(hp, sp) for sp in sps]
+    sims = [_prepare(hp, sp) for sp in sps]
+    hp.Batch(sims).sweep(20, counters=False)  # the untimed melt, all replicas together
+    sims = [_finish(x, sp) for x, sp in zip(sims, sps)]
     tuning = None
     if args.autotune:
         # the batch launches with the shape of its first handle: tune the largest replica
@@ -455,18 +484,20 @@ def bench_c4(args):
         c = {k: sum(x[k] for x in cs) for k in cs[0]}
         tot = c if tot is None else {k: tot[k] + c[k] for k in tot}
     dt = time.perf_counter() - t0
+    alone = None
     # the same replicas swept one at a time (each handle's own launches), for comparison
-    for x in sims:
+    for x in (sims if args.alone else []):
         x.sweep(1, counters=False)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(2):
-        for x in sims:
-            x.sweep(1, counters=False)
-    torch.cuda.synchronize()
-    dt1 = time.perf_counter() - t1
-    alone = {"moves_per_s": 2 * sum(x.n for x in sims) / dt1, "ms_per_sweep": dt1 * 1e3 / 2,
-             "note": "the same replicas, each swept alone in turn (2 sweeps)"}
+    if args.alone:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(2):
+            for x in sims:
+                x.sweep(1, counters=False)
+        torch.cuda.synchronize()
+        dt1 = time.perf_counter() - t1
+        alone = {"moves_per_s": 2 * sum(x.n for x in sims) / dt1, "ms_per_sweep": dt1 * 1e3 / 2,
+                 "note": "the same replicas, each swept alone in turn (2 sweeps)"}
     return _line(tot["trials"] / dt, tot, dt, args.steps, 3,
                  f"256 swept-disk replicas, N={sum(s.n for s in sps)} in total (128..8192 each), "
                  "phi_c U[0.05,0.45], eta_r U[0,0.5], q=0.2, one launch per kernel for all replicas",
