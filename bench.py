@@ -525,6 +525,7 @@ def bench_c5(args):
     dt = time.perf_counter() - t0
     summ = serve.latency_summary(done)
     errors = sum(1 for r in done if "error" in r.result)
+    offered = sum(sp.n * sp.extra["sweeps"] for sp in specs) / args.serve_seconds
     # capacity with every request of a sample available at once: continuous
     # batching against one request at a time, same requests and work
     sample = specs[: args.capacity_requests]
@@ -558,6 +559,11 @@ def bench_c5(args):
         "p99_ms": summ["p99_s"] * 1e3,
         "requests": summ["requests"],
         "failed_requests": errors,
+        "offered_load_moves_per_s": offered,
+        "achieved_moves_per_s": srv.moves / dt,
+        "max_active_requests": max((n for _, _, n in srv.ticks), default=0),
+        "max_bytes_held": max((u for _, u, _ in srv.ticks), default=0),
+        "hbm_budget": srv.budget,
         "latency_note": "per request, arrival to observables returned",
         "capacity": cap,
     }

@@ -187,8 +187,12 @@ int hpmc_set_workspace(hpmc_sim* sim, void* dev_ptr, size_t bytes);
  * that no two colloids overlap.  Errors: EINVAL, ESTATE, EOVERLAP, EHIP. */
 int hpmc_set_state(hpmc_sim* sim, double* pos_soa, double* quat_soa, uint64_t sweep_index);
 
-/* Current sweep index (the state itself is in the caller's buffers). */
-int hpmc_get_state(const hpmc_sim* sim, uint64_t* sweep_index);
+/* Current sweep index (the state itself is in the caller's buffers).
+ * Synchronises the handle's stream, so the state buffers hold the result of
+ * every sweep enqueued so far.  Errors: EINVAL, ESTATE, EHIP, ECAPACITY (a
+ * sweep since the last report skipped a cell whose stencil exceeded its
+ * capacity; reported once, by this or the next synchronising call). */
+int hpmc_get_state(hpmc_sim* sim, uint64_t* sweep_index);
 
 /* Record one hpmc_move_record per trial of the most recent sweep (parity
  * mode).  Enabling it grows hpmc_workspace_bytes; device calls return ENOMEM
@@ -197,7 +201,12 @@ int hpmc_set_trace(hpmc_sim* sim, int enable);
 
 /* Run n_sweeps sweeps, enqueued on the stream.  If out is non-NULL the call
  * synchronises and fills the counters summed over these sweeps (host).
- * Errors: ESTATE, ENOMEM, EHIP, ECAPACITY (checked when out is non-NULL). */
+ * Errors: ESTATE, ENOMEM, EHIP, ECAPACITY.  ECAPACITY means that a cell's
+ * stencil exceeded the packing bound its lists are sized by, which disjoint
+ * bodies cannot reach; its trials were skipped.  The device flag behind it is
+ * sticky: it is reported once, by the first synchronising call after the
+ * sweep that raised it (this call with out non-NULL, hpmc_get_state,
+ * hpmc_observables, hpmc_trace), and cleared by that report. */
 int hpmc_sweep(hpmc_sim* sim, int n_sweeps, hpmc_counters* out);
 
 /* Launch shape of the phase kernels.  It never changes a result (every
@@ -237,9 +246,11 @@ int hpmc_batch_workspace_bytes(int n_sims, size_t* bytes);
  * its own state, workspace and random streams, so every replica's trajectory
  * is identical to what hpmc_sweep gives it alone.  All handles must be ready
  * (shape, workspace, state) and use the stream of sims[0]; tracing must be
- * off.  batch_ws: device scratch of hpmc_batch_workspace_bytes(n_sims).  out:
- * NULL or n_sims counter records (synchronises).  Errors: EINVAL, ESTATE,
- * ENOMEM, EHIP, ECAPACITY. */
+ * off.  batch_ws: device scratch of hpmc_batch_workspace_bytes(n_sims); the
+ * descriptors are copied into it on the stream from pinned host staging
+ * buffers of sims[0], so the call does not wait for the device unless out is
+ * given.  out: NULL or n_sims counter records (synchronises).  Errors: EINVAL,
+ * ESTATE, ENOMEM, EHIP, ECAPACITY (as for hpmc_sweep, per replica). */
 int hpmc_sweep_batch(hpmc_sim* const* sims, int n_sims, void* batch_ws, size_t bytes, int n_sweeps,
                      hpmc_counters* out);
 
@@ -252,11 +263,13 @@ int hpmc_sweep_batch(hpmc_sim* const* sims, int n_sims, void* batch_ws, size_t b
  *   HPMC_OBS_SDF: out[0] = beta P total, out[1] = rho (1 + s(0+)/6),
  *     out[2] = z_p dV_f/dV (virtual expansion of the probe set), out[3] = s(0+),
  *     out[4..4+n_bins) = s(x) histogram of the per-particle minimum compression.
- * Errors: EINVAL, ESTATE, ENOMEM, EHIP. */
+ * Errors: EINVAL, ESTATE, ENOMEM, EHIP, ECAPACITY (a pending capacity flag of
+ * an earlier sweep, see hpmc_sweep). */
 int hpmc_observables(hpmc_sim* sim, int kind, const hpmc_obs_params* params, double* out, int64_t out_len);
 
 /* Copy the trace of the most recent sweep (host buf, cap records); requires
- * hpmc_set_trace(sim, 1) before that sweep.  Errors: ESTATE, EHIP. */
+ * hpmc_set_trace(sim, 1) before that sweep.  Errors: ESTATE, EHIP, ECAPACITY
+ * (a pending capacity flag, see hpmc_sweep). */
 int hpmc_trace(hpmc_sim* sim, hpmc_move_record* buf, int64_t cap, int64_t* n_written);
 
 #ifdef __cplusplus

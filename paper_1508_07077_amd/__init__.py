@@ -294,20 +294,30 @@ class Sim:
 
 
 class Batch:
-    """Several independent handles swept in shared launches (hpmc_sweep_batch)."""
+    """Several independent handles swept in shared launches (hpmc_sweep_batch).
+    The batch workspace is allocated once for `capacity` handles (default: as
+    many as given); set_members changes the membership without reallocating."""
 
-    def __init__(self, sims):
+    def __init__(self, sims, capacity: int | None = None, device=None):
         import torch
 
-        self.sims = list(sims)
         self.torch = torch
-        n = len(self.sims)
+        self.sims = list(sims)
+        cap = max(len(self.sims), int(capacity or 0), 1)
+        dev = torch.device(device) if device is not None else self.sims[0].device
         b = ctypes.c_size_t(0)
-        rc = lib().hpmc_batch_workspace_bytes(n, ctypes.byref(b))
+        rc = lib().hpmc_batch_workspace_bytes(cap, ctypes.byref(b))
         if rc != 0:
             raise HpmcError(rc, "hpmc_batch_workspace_bytes")
-        self.workspace = torch.empty(int(b.value), dtype=torch.uint8, device=self.sims[0].device)
-        self._handles = (ctypes.c_void_p * n)(*[s._h.value for s in self.sims])
+        self.capacity = cap
+        self.workspace = torch.empty(int(b.value), dtype=torch.uint8, device=dev)
+        self.set_members(self.sims)
+
+    def set_members(self, sims):
+        if len(sims) > self.capacity:
+            raise ValueError(f"{len(sims)} handles exceed the batch capacity {self.capacity}")
+        self.sims = list(sims)
+        self._handles = (ctypes.c_void_p * max(len(self.sims), 1))(*[s._h.value for s in self.sims])
 
     def sweep(self, n_sweeps: int = 1, counters: bool = True):
         n = len(self.sims)
@@ -315,7 +325,7 @@ class Batch:
         rc = lib().hpmc_sweep_batch(self._handles, n, ctypes.c_void_p(self.workspace.data_ptr()),
                                     self.workspace.numel(), int(n_sweeps), out)
         if rc != 0:
-            msg = lib().hpmc_last_error(self.sims[0]._h)
+            msg = lib().hpmc_last_error(self.sims[0]._h) if n else b""
             raise HpmcError(rc, f"sweep_batch: {msg.decode() if msg else ''}")
         if not counters:
             return None

@@ -67,6 +67,14 @@ struct hpmc_sim {
     hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
     Desc desc{};                     // host copy of the device descriptor
     Desc* d_desc = nullptr;          // device descriptor (in the workspace)
+    // pinned staging buffers of the descriptors of batched sweeps led by this
+    // handle, used in turn, each with the event after its last upload (a
+    // buffer is rewritten only once its copy is done)
+    static constexpr int kStages = 4;
+    Desc* batch_stage[kStages] = {};
+    size_t batch_stage_cap[kStages] = {};
+    hipEvent_t batch_up[kStages] = {};
+    int batch_next = 0;
     unsigned long long* d_gather = nullptr;
     int desc_dirty = 1;
     std::string err;
@@ -79,6 +87,13 @@ struct hpmc_sim {
             if (join[i]) (void)hipEventDestroy(join[i]);
         }
         if (fork) (void)hipEventDestroy(fork);
+        for (int i = 0; i < kStages; ++i) {
+            if (batch_up[i]) {
+                (void)hipEventSynchronize(batch_up[i]);
+                (void)hipEventDestroy(batch_up[i]);
+            }
+            if (batch_stage[i]) (void)hipHostFree(batch_stage[i]);
+        }
     }
 };
 
@@ -243,7 +258,7 @@ Params make_params(const hpmc_sim* s)
     P.precision = s->precision;
     P.key0 = static_cast<uint32_t>(s->seed & 0xFFFFFFFFu);
     P.key1 = static_cast<uint32_t>(s->seed >> 32) ^ s->replica;
-    P.sweep = static_cast<uint32_t>(s->sweep);
+    P.sweep = 0;  // kernels read the sweep index from the workspace's device counter
     P.L = s->L;
     P.halfL = s->halfL;
     P.w = s->w;
@@ -426,6 +441,27 @@ int upload_table(hpmc_sim* s)
     return HPMC_OK;
 }
 
+// Capacity flags are sticky: a kernel that had to skip work sets them, and
+// they stay set until a synchronising call reports them (ECAPACITY) and
+// clears them, so untimed and graph-replayed sweeps cannot lose one.
+int report_flags(hpmc_sim* s, int flags)
+{
+    if (!flags) return HPMC_OK;
+    hipError_t e = launch_fill_int(s->W.flags, 4, 0, s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "clear flags");
+    return fail(s, HPMC_ECAPACITY, "a cell's stencil exceeded its capacity in an earlier sweep; its trials were "
+                                   "skipped (flags " + std::to_string(flags) + ")");
+}
+
+int check_flags(hpmc_sim* s)
+{
+    int flags = 0;
+    hipError_t e = hipMemcpyAsync(&flags, s->W.flags, sizeof(int), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "read flags");
+    return report_flags(s, flags);
+}
+
 }  // namespace
 
 extern "C" {
@@ -574,10 +610,17 @@ int hpmc_set_workspace(hpmc_sim* s, void* dev_ptr, size_t bytes)
     if (!dev_ptr) return fail(s, HPMC_EINVAL, "null workspace");
     if (!s->have_shape) return fail(s, HPMC_ESTATE, "shape not set");
     if (bytes < layout(s).total) return fail(s, HPMC_ENOMEM, "workspace too small");
+    const bool fresh = dev_ptr != s->ws;
     s->ws = dev_ptr;
     s->ws_bytes = bytes;
     s->F_dirty = 1;
     bind_work(s);
+    if (!s->stream) s->stream = library_stream();
+    if (fresh) {
+        // new memory: no capacity flag raised yet (the same buffer keeps a pending one)
+        hipError_t e = launch_fill_int(s->W.flags, 4, 0, s->stream);
+        if (e != hipSuccess) return hip_fail(s, e, "clear flags");
+    }
     // the device-side sweep counter lives in the workspace: carry it over
     if (s->have_state) return set_sweep_dev(s);
     return HPMC_OK;
@@ -632,12 +675,14 @@ int hpmc_set_state(hpmc_sim* s, double* pos, double* quat, uint64_t sweep_index)
     return HPMC_OK;
 }
 
-int hpmc_get_state(const hpmc_sim* s, uint64_t* sweep_index)
+int hpmc_get_state(hpmc_sim* s, uint64_t* sweep_index)
 {
     if (!s || !sweep_index) return HPMC_EINVAL;
     if (!s->have_state) return HPMC_ESTATE;
     *sweep_index = s->sweep;
-    return HPMC_OK;
+    // the state is final once the stream has drained; a capacity flag raised
+    // by the sweeps since the last report is reported here
+    return s->ws ? check_flags(s) : HPMC_OK;
 }
 
 namespace {
@@ -774,9 +819,7 @@ int hpmc_sweep(hpmc_sim* s, int n_sweeps, hpmc_counters* out)
         if (e != hipSuccess) return hip_fail(s, e, "hipEventElapsedTime");
         out->phase_kernel_ms = phase_ms;
         out->sweep_ms = all;
-        if (host[kNumCounters])
-            return fail(s, HPMC_ECAPACITY,
-                        "stencil or cell capacity exceeded (flags " + std::to_string(host[kNumCounters]) + ")");
+        return report_flags(s, static_cast<int>(host[kNumCounters]));
     }
     return HPMC_OK;
 }
@@ -880,6 +923,39 @@ int hpmc_autotune(hpmc_sim* s, void* scratch, size_t bytes, int sweeps, hpmc_tun
     return HPMC_OK;
 }
 
+namespace {
+
+// Descriptors of a batched sweep go to the batch workspace from one of the
+// leader's pinned staging buffers, with no host synchronisation: the copy is
+// ordered on the stream after the previous call's kernels, and a staging
+// buffer is rewritten only once its previous copy completed (with four in
+// turn, the host may enqueue that many calls ahead of the device).
+int upload_batch_descs(hpmc_sim* lead, Desc* d_all, const std::vector<Desc>& host, hipStream_t st)
+{
+    const size_t bytes = host.size() * sizeof(Desc);
+    const int k = lead->batch_next;
+    lead->batch_next = (k + 1) % hpmc_sim::kStages;
+    hipError_t e = hipSuccess;
+    if (lead->batch_up[k]) e = hipEventSynchronize(lead->batch_up[k]);
+    if (e == hipSuccess && lead->batch_stage_cap[k] < host.size()) {
+        if (lead->batch_stage[k]) e = hipHostFree(lead->batch_stage[k]);
+        lead->batch_stage[k] = nullptr;
+        lead->batch_stage_cap[k] = 0;
+        if (e == hipSuccess)
+            e = hipHostMalloc(reinterpret_cast<void**>(&lead->batch_stage[k]), bytes, hipHostMallocDefault);
+        if (e == hipSuccess) lead->batch_stage_cap[k] = host.size();
+    }
+    if (e == hipSuccess && !lead->batch_up[k]) e = hipEventCreateWithFlags(&lead->batch_up[k], hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(lead, e, "batch descriptor staging");
+    memcpy(lead->batch_stage[k], host.data(), bytes);
+    e = hipMemcpyAsync(d_all, lead->batch_stage[k], bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipEventRecord(lead->batch_up[k], st);
+    if (e != hipSuccess) return hip_fail(lead, e, "batch descriptor upload");
+    return HPMC_OK;
+}
+
+}  // namespace
+
 int hpmc_batch_workspace_bytes(int n_sims, size_t* bytes)
 {
     if (n_sims < 1 || !bytes) return HPMC_EINVAL;
@@ -939,8 +1015,9 @@ int hpmc_sweep_batch(hpmc_sim* const* sims, int n_sims, void* batch_ws, size_t b
         groups.push_back(g);
         b = e;
     }
-    hipError_t e = hipMemcpyAsync(d_all, host.data(), host.size() * sizeof(Desc), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);  // the host copy is a local
+    int ru = upload_batch_descs(sims[0], d_all, host, st);
+    if (ru != HPMC_OK) return ru;
+    hipError_t e = hipSuccess;
     for (const Group& g : groups)
         if (e == hipSuccess) e = launch_clear_counters(g, st);
     if (e == hipSuccess) e = run_sweeps(sims[0], groups, n_sweeps, st);
@@ -957,12 +1034,20 @@ int hpmc_sweep_batch(hpmc_sim* const* sims, int n_sims, void* batch_ws, size_t b
             e = hipMemcpyAsync(hc.data(), d_gather, hc.size() * 8, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(sims[0], e, "batched counters");
-        int flags = 0;
+        int r = HPMC_OK;
         for (size_t q = 0; q < order.size(); ++q) {
             unpack_counters(&hc[q * kCounterStride], &out[order[q]]);
-            flags |= static_cast<int>(hc[q * kCounterStride + kNumCounters]);
+            const int f = static_cast<int>(hc[q * kCounterStride + kNumCounters]);
+            if (f) {
+                hpmc_sim* x = sims[order[q]];
+                int rq = report_flags(x, f);
+                if (r == HPMC_OK) {
+                    r = rq;
+                    if (x != sims[0]) fail(sims[0], rq, "replica " + std::to_string(order[q]) + ": " + x->err);
+                }
+            }
         }
-        if (flags) return fail(sims[0], HPMC_ECAPACITY, "stencil or cell capacity exceeded in a batched sweep");
+        return r;
     }
     return HPMC_OK;
 }
@@ -972,6 +1057,8 @@ int hpmc_trace(hpmc_sim* s, hpmc_move_record* buf, int64_t cap, int64_t* n_writt
     if (!s || !n_written || (cap > 0 && !buf)) return HPMC_EINVAL;
     *n_written = 0;
     if (!s->trace || !s->trace_valid) return fail(s, HPMC_ESTATE, "no traced sweep");
+    int rf = check_flags(s);
+    if (rf != HPMC_OK) return rf;
     int64_t n = s->N * s->n_select;
     if (n > cap) n = cap;
     if (n > 0) {
@@ -989,8 +1076,8 @@ int hpmc_observables(hpmc_sim* s, int kind, const hpmc_obs_params* p, double* ou
     if (!s) return HPMC_EINVAL;
     if (!p || !out) return fail(s, HPMC_EINVAL, "null observable arguments");
     int r = check_ready(s, true);
-    if (r != HPMC_OK) return r;
-    r = sync_desc(s);
+    if (r == HPMC_OK) r = sync_desc(s);
+    if (r == HPMC_OK) r = check_flags(s);
     if (r != HPMC_OK) return r;
     Params P = make_params(s);
     Group g = single_group(s);

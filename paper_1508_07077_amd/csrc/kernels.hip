@@ -466,7 +466,6 @@ __global__ void clear_counters_kernel(const Desc* __restrict__ D)
     const Work W = D[blockIdx.y].W;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < kCounterCopies * kCounterStride) W.counters[i] = 0ull;
-    if (i < 4) W.flags[i] = 0;
 }
 
 __global__ void clear_cells_kernel(const Desc* __restrict__ D)
@@ -1217,7 +1216,7 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
             nst_next = stage_issue(P, W, stage_buf(buf ^ 1), es, ec);
             ranges_of(kn2, es, ec);
         }
-        if (nst < 0 || nc > kStage) {
+        if (nst < 0) {
             if (lane == 0) atomicOr(W.flags, kFlagListOverflow);
         } else {
             const int ntr = P.n_select * nc;
@@ -1236,7 +1235,8 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
                 }
                 Words w = draw(P, static_cast<uint32_t>(C), static_cast<uint32_t>(t), purpose, index);
                 const int jl = static_cast<int>(pick(rdlane_u(w.w0, 0), static_cast<uint32_t>(nc)));
-                const double4 pj = stage_rec(S0, jl);  // own members are entries 0 .. nc-1
+                // own members are entries 0 .. nc-1: staged, or (past the stage) in HBM
+                const double4 pj = jl < kStage ? stage_rec(S0, jl) : W.rpos[start + jl];
                 Vec3 xn;
                 {
                     uint32_t tw0 = rdlane_u(w.w0, 1), tw1 = rdlane_u(w.w1, 1), tw2 = rdlane_u(w.w2, 1);
@@ -1264,6 +1264,7 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
                     // hard overlap with another colloid
                     bool hit = dot(Dreg, Dreg) < P.S.dsq;
                     for (int i = kStage + lane; i < nst; i += 64) {
+                        if (i == jl) continue;  // the moved colloid itself (a member past the stage)
                         double4 r = W.rpos[S0.list[i]];
                         Vec3 D = v3(mi(P, r.x - xn.x), mi(P, r.y - xn.y), mi(P, r.z - xn.z));
                         hit = hit || dot(D, D) < P.S.dsq;
@@ -1327,6 +1328,7 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
                                 uint32_t ks = rdlane_u(cand ? k1 : k0, src);
                                 bool h = sphere_in<F32>(P, es3, Dreg, true, fallbacks);
                                 for (int i = kStage + lane; i < nst; i += 64) {
+                                    if (i == jl) continue;
                                     double4 r = W.rpos[S0.list[i]];
                                     Vec3 D = v3(mi(P, r.x - xn.x), mi(P, r.y - xn.y), mi(P, r.z - xn.z));
                                     h = h || dot(es3 - D, es3 - D) < P.S.R0sq;
@@ -1396,9 +1398,15 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
                 }
                 // --- accept / commit / record -----------------------------------
                 if (o.reason == 0 && lane == 0) {
-                    S0.recA[2 * jl] = xn.x;
-                    S0.recA[2 * jl + 1] = xn.y;
-                    S0.recB[2 * jl] = xn.z;
+                    if (jl < kStage) {
+                        S0.recA[2 * jl] = xn.x;
+                        S0.recA[2 * jl + 1] = xn.y;
+                        S0.recB[2 * jl] = xn.z;
+                    } else {
+                        // a member past the stage: its record is updated in place (only this
+                        // wave reads the cell's members during the phase)
+                        W.rpos[start + jl] = make_double4(xn.x, xn.y, xn.z, pj.w);
+                    }
                 }
                 wave_sync();
                 if (lane == 0) {
@@ -1423,8 +1431,8 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
                     r[9] = static_cast<uint32_t>(phase) | (static_cast<uint32_t>(o.reason) << 8);
                 }
             }
-            // own-cell records back to HBM
-            for (int i = lane; i < nc; i += 64) W.rpos[start + i] = stage_rec(S0, i);
+            // staged own-cell records back to HBM
+            for (int i = lane; i < nc && i < kStage; i += 64) W.rpos[start + i] = stage_rec(S0, i);
         }
         kc = kn;
         kn = kn2;
