@@ -184,7 +184,9 @@ int hpmc_set_workspace(hpmc_sim* sim, void* dev_ptr, size_t bytes);
  * doubles (required for oriented shapes, ignored for spheres), both kept for
  * the lifetime of the handle; sweeps update them in place.  sweep_index sets
  * the sweep counter of the random streams.  Synchronises the stream and checks
- * that no two colloids overlap.  Errors: EINVAL, ESTATE, EOVERLAP, EHIP. */
+ * that no two colloids overlap (in the caller's workspace, or, when none is
+ * set, in the static scratch of hpmc_sweep_static).  Errors: EINVAL, ESTATE,
+ * EOVERLAP, EHIP, ENOMEM (no workspace and more than the static scratch). */
 int hpmc_set_state(hpmc_sim* sim, double* pos_soa, double* quat_soa, uint64_t sweep_index);
 
 /* Current sweep index (the state itself is in the caller's buffers).
@@ -208,6 +210,27 @@ int hpmc_set_trace(hpmc_sim* sim, int enable);
  * sweep that raised it (this call with out non-NULL, hpmc_get_state,
  * hpmc_observables, hpmc_trace), and cleared by that report. */
 int hpmc_sweep(hpmc_sim* sim, int n_sweeps, hpmc_counters* out);
+
+/* Allocation-free variant of hpmc_sweep, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  It runs the same kernels as hpmc_sweep, with the
+ * handle's workspace laid out in the library's static scratch instead of the
+ * caller's buffer: a file-scope device array of 64 MiB (one copy per device,
+ * held until the process ends) on the current device.  The call allocates
+ * nothing; the caller still owns the state (hpmc_set_state; without a
+ * workspace, its one-time hard-core check also runs in the static scratch).
+ * Needs shape and state; tracing off.  Each call writes the descriptor,
+ * Poisson table, sweep counter and cleared flags into the scratch before its
+ * sweeps, so a call does not depend on what an earlier one left there; calls
+ * on one device share the one array, so calls that overlap on a device (two
+ * streams, two threads) race and must be serialised by the caller.  The
+ * handle's own workspace, if set, is not touched; its sweep counter is brought
+ * up to date by the next call that uses it.  out: as for hpmc_sweep, except
+ * that phase_kernel_ms and sweep_ms are 0 (no events are recorded).  Errors:
+ * EINVAL, ESTATE, ENOMEM (the handle needs more than 64 MiB of scratch; about
+ * 76 bytes per sphere, 108 per oriented body, plus 8 per cell), EHIP,
+ * ECAPACITY (reported only when out is non-NULL). */
+int hpmc_sweep_static(hpmc_sim* sim, int n_sweeps, hpmc_counters* out);
 
 /* Launch shape of the phase kernels.  It never changes a result (every
  * random draw is keyed by sweep, cell, round and purpose, not by thread), only

@@ -45,6 +45,7 @@ EXPORTS = (
     "hpmc_get_state",
     "hpmc_set_trace",
     "hpmc_sweep",
+    "hpmc_sweep_static",
     "hpmc_observables",
     "hpmc_trace",
     "hpmc_batch_workspace_bytes",
@@ -138,6 +139,7 @@ def lib():
         L.hpmc_get_state.argtypes = [vp, ctypes.POINTER(u64)]
         L.hpmc_set_trace.argtypes = [vp, cint]
         L.hpmc_sweep.argtypes = [vp, cint, ctypes.POINTER(_Counters)]
+        L.hpmc_sweep_static.argtypes = [vp, cint, ctypes.POINTER(_Counters)]
         L.hpmc_observables.argtypes = [vp, cint, ctypes.POINTER(_ObsParams), dp, i64]
         L.hpmc_trace.argtypes = [vp, vp, i64, ctypes.POINTER(i64)]
         L.hpmc_batch_workspace_bytes.argtypes = [cint, ctypes.POINTER(ctypes.c_size_t)]
@@ -227,10 +229,12 @@ class Sim:
         self._chk(lib().hpmc_set_workspace(self._h, ctypes.c_void_p(self.workspace.data_ptr()),
                                            self.workspace.numel()), "set_workspace")
 
-    def set_state(self, pos, quat=None, sweep: int = 0):
-        """pos [3][n], quat [4][n] (oriented shapes): host arrays or device tensors."""
+    def set_state(self, pos, quat=None, sweep: int = 0, workspace: bool = True):
+        """pos [3][n], quat [4][n] (oriented shapes): host arrays or device tensors.
+        workspace=False allocates no workspace (for sweep_static only)."""
         torch = self.torch
-        self.ensure_workspace()
+        if workspace:
+            self.ensure_workspace()
         self.pos = torch.as_tensor(np.asarray(pos) if not torch.is_tensor(pos) else pos, dtype=torch.float64)
         self.pos = self.pos.reshape(3, self.n).to(self.device).contiguous()
         qptr = None
@@ -258,6 +262,17 @@ class Sim:
             d["phase_kernel_ms"] = float(c.phase_kernel_ms)
             d["sweep_ms"] = float(c.sweep_ms)
             return d
+        return None
+
+    def sweep_static(self, n_sweeps: int = 1, counters: bool = True):
+        """hpmc_sweep_static: the same sweeps with the library's static device
+        scratch as workspace (allocates nothing; calls on one device must not
+        overlap)."""
+        c = _Counters()
+        self._chk(lib().hpmc_sweep_static(self._h, int(n_sweeps), ctypes.byref(c) if counters else None),
+                  "sweep_static")
+        if counters:
+            return {f: int(getattr(c, f)) for f in COUNTERS}
         return None
 
     def set_tuning(self, cells_per_wave: int = 0, waves_per_block: int = 0, max_waves: int = 0):

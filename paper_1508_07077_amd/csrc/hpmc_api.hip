@@ -19,6 +19,13 @@
 
 using namespace hpmc;
 
+// Static scratch of the allocation-free entry point (hpmc_sweep_static): a
+// file-scope device array, one copy per device, held until the process ends.
+// Host code never passes the array's name to a kernel: it uses the address
+// that hipGetSymbolAddress returns for the current device.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 struct hpmc_sim {
     int64_t N = 0;
     double L = 0, halfL = 0;
@@ -59,6 +66,8 @@ struct hpmc_sim {
     int trace = 0;
     int trace_valid = 0;
     std::vector<hipEvent_t> events;  // timing of phase launches (counters requested)
+    int sweep_dev_stale = 0;         // the workspace's sweep counter lags (hpmc_sweep_static ran)
+    Desc static_desc{};              // host copy of the descriptor in the static scratch
     hipGraphExec_t graph = nullptr;  // one captured sweep, replayed for untimed multi-sweep calls
     std::vector<unsigned char> graph_key;
     // side streams (default priority) that let the shape groups of a batched
@@ -205,11 +214,11 @@ Layout layout(const hpmc_sim* s)
     return l;
 }
 
-void bind_work(hpmc_sim* s)
+// the workspace regions of handle s carved out of the buffer at b
+Work carve(const hpmc_sim* s, unsigned char* b, Desc** d_desc, unsigned long long** d_gather)
 {
     Layout l = layout(s);
-    unsigned char* b = static_cast<unsigned char*>(s->ws);
-    Work& W = s->W;
+    Work W{};
     W.cell_count = reinterpret_cast<int*>(b + l.cell_count);
     W.cell_start = reinterpret_cast<int*>(b + l.cell_start);
     W.scan_tmp = reinterpret_cast<int*>(b + l.scan_tmp);
@@ -228,8 +237,14 @@ void bind_work(hpmc_sim* s)
     W.sweep_dev = reinterpret_cast<uint32_t*>(b + l.sweep);
     W.pos = s->pos;
     W.quat = s->quat;
-    s->d_desc = reinterpret_cast<Desc*>(b + l.desc);
-    s->d_gather = reinterpret_cast<unsigned long long*>(b + l.gather);
+    *d_desc = reinterpret_cast<Desc*>(b + l.desc);
+    *d_gather = reinterpret_cast<unsigned long long*>(b + l.gather);
+    return W;
+}
+
+void bind_work(hpmc_sim* s)
+{
+    s->W = carve(s, static_cast<unsigned char*>(s->ws), &s->d_desc, &s->d_gather);
     s->desc_dirty = 1;
 }
 
@@ -427,6 +442,11 @@ int check_ready(hpmc_sim* s, bool need_state)
     Params P = make_params(s);
     if (kTableLds + static_cast<size_t>(P.waves_per_block) * P.wave_lds > 64 * 1024)
         return fail(s, HPMC_ECAPACITY, "stencil too large for the LDS of one workgroup");
+    if (s->sweep_dev_stale && s->have_state) {
+        int r = set_sweep_dev(s);
+        if (r != HPMC_OK) return r;
+        s->sweep_dev_stale = 0;
+    }
     return HPMC_OK;
 }
 
@@ -451,6 +471,61 @@ int report_flags(hpmc_sim* s, int flags)
     if (e != hipSuccess) return hip_fail(s, e, "clear flags");
     return fail(s, HPMC_ECAPACITY, "a cell's stencil exceeded its capacity in an earlier sweep; its trials were "
                                    "skipped (flags " + std::to_string(flags) + ")");
+}
+
+// Address of the static scratch on each device (set up once per device, with
+// that device current).
+std::mutex g_scratch_mu;
+void* g_scratch[64] = {};
+
+int static_scratch(hpmc_sim* s, unsigned char** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(s, e, "hipGetDevice");
+    if (dev < 0 || dev >= 64) return fail(s, HPMC_EINVAL, "device index beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(s, e, "hipGetSymbolAddress(static scratch)");
+        if (!p) return fail(s, HPMC_EHIP, "hipGetSymbolAddress(static scratch) returned a null address");
+        g_scratch[dev] = p;
+    }
+    *out = static_cast<unsigned char*>(g_scratch[dev]);
+    return HPMC_OK;
+}
+
+// Lay the handle's workspace out in the static scratch of the current device
+// and enqueue its descriptor, Poisson table, sweep counter and cleared flags
+// there.  Whatever an earlier call left in the scratch is overwritten.
+int bind_static(hpmc_sim* s, Group& g, Work& W, unsigned long long** gather)
+{
+    const size_t need = layout(s).total;
+    if (need > kStaticScratchBytes)
+        return fail(s, HPMC_ENOMEM, "this handle needs " + std::to_string(need) + " bytes of scratch; the static "
+                                    "scratch holds " + std::to_string(kStaticScratchBytes));
+    Params P = make_params(s);
+    if (kTableLds + static_cast<size_t>(P.waves_per_block) * P.wave_lds > 64 * 1024)
+        return fail(s, HPMC_ECAPACITY, "stencil too large for the LDS of one workgroup");
+    unsigned char* base = nullptr;
+    int r = static_scratch(s, &base);
+    if (r != HPMC_OK) return r;
+    Desc* d_desc = nullptr;
+    W = carve(s, base, &d_desc, gather);
+    s->static_desc = make_desc(s, P.waves_per_block, P.chunk);
+    s->static_desc.W = W;
+    hipError_t e = hipMemcpyAsync(d_desc, &s->static_desc, sizeof(Desc), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(W.F, s->F, sizeof(s->F), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(W.F + kPoissonK, s->G, sizeof(s->G), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+        e = launch_fill_int(reinterpret_cast<int*>(W.sweep_dev), 1, static_cast<int>(static_cast<uint32_t>(s->sweep)),
+                            s->stream);
+    if (e == hipSuccess) e = launch_fill_int(W.flags, 4, 0, s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "static scratch set-up");
+    const hpmc_sim* one[1] = {s};
+    g = make_group(d_desc, one, 1);
+    return HPMC_OK;
 }
 
 int check_flags(hpmc_sim* s)
@@ -636,11 +711,46 @@ int hpmc_set_trace(hpmc_sim* s, int enable)
     return HPMC_OK;
 }
 
+namespace {
+
+// hpmc_set_state on a handle without a workspace: the state is taken and its
+// hard-core check runs in the static scratch of the current device
+int set_state_static(hpmc_sim* s, double* pos, double* quat, uint64_t sweep_index)
+{
+    if (!s->stream) s->stream = library_stream();
+    s->pos = pos;
+    s->quat = s->S.oriented ? quat : nullptr;
+    s->W.pos = s->pos;
+    s->W.quat = s->quat;
+    s->sweep = sweep_index;
+    s->trace_valid = 0;
+    s->have_state = 0;
+    Group g{};
+    Work W{};
+    unsigned long long* gather = nullptr;
+    int r = bind_static(s, g, W, &gather);
+    if (r != HPMC_OK) return r;
+    hipError_t e = launch_build_cells(g, false, s->stream);
+    if (e == hipSuccess) e = launch_fill_u64(W.obs, 1, s->stream);
+    if (e == hipSuccess) e = launch_overlap_count(g, s->stream);
+    unsigned long long cnt = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&cnt, W.obs, 8, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "set_state");
+    if (cnt > 0) return fail(s, HPMC_EOVERLAP, std::to_string(cnt) + " overlapping colloid pairs");
+    s->have_state = 1;
+    s->sweep_dev_stale = 1;  // a workspace set later gets the sweep counter
+    return HPMC_OK;
+}
+
+}  // namespace
+
 int hpmc_set_state(hpmc_sim* s, double* pos, double* quat, uint64_t sweep_index)
 {
     if (!s) return HPMC_EINVAL;
     if (!pos) return fail(s, HPMC_EINVAL, "null positions");
     if (s->have_shape && s->S.oriented && !quat) return fail(s, HPMC_EINVAL, "oriented shape needs quaternions");
+    if (s->have_shape && !s->ws) return set_state_static(s, pos, quat, sweep_index);
     int r = check_ready(s, false);
     if (r != HPMC_OK) return r;
     s->pos = pos;
@@ -820,6 +930,42 @@ int hpmc_sweep(hpmc_sim* s, int n_sweeps, hpmc_counters* out)
         out->phase_kernel_ms = phase_ms;
         out->sweep_ms = all;
         return report_flags(s, static_cast<int>(host[kNumCounters]));
+    }
+    return HPMC_OK;
+}
+
+int hpmc_sweep_static(hpmc_sim* s, int n_sweeps, hpmc_counters* out)
+{
+    if (!s) return HPMC_EINVAL;
+    if (n_sweeps < 0) return fail(s, HPMC_EINVAL, "negative sweep count");
+    if (!s->stream) s->stream = library_stream();
+    if (!s->have_shape) return fail(s, HPMC_ESTATE, "shape not set");
+    if (!s->have_state) return fail(s, HPMC_ESTATE, "state not set");
+    if (s->trace) return fail(s, HPMC_EINVAL, "tracing writes into the caller's workspace; use hpmc_sweep");
+    Group g{};
+    Work W{};
+    unsigned long long* gather = nullptr;
+    int r = bind_static(s, g, W, &gather);
+    if (r != HPMC_OK) return r;
+    hipError_t e = launch_clear_counters(g, s->stream);
+    if (g.small) {
+        if (e == hipSuccess && n_sweeps > 0) e = launch_sweep_small(g, n_sweeps, s->stream);
+    } else {
+        for (int i = 0; i < n_sweeps && e == hipSuccess; ++i) e = launch_sweep(g, nullptr, nullptr, s->stream);
+    }
+    if (e != hipSuccess) return hip_fail(s, e, "static sweep launch");
+    s->sweep += static_cast<uint64_t>(n_sweeps);
+    s->sweep_dev_stale = 1;  // the caller's workspace, if any, still holds the old sweep index
+    s->trace_valid = 0;
+    if (out) {
+        unsigned long long host[kCounterStride];
+        e = launch_reduce_counters(g, gather, s->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(host, gather, sizeof(host), hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return hip_fail(s, e, "static sweep counters");
+        unpack_counters(host, out);
+        if (host[kNumCounters])
+            return fail(s, HPMC_ECAPACITY, "a cell's stencil exceeded its capacity; its trials were skipped");
     }
     return HPMC_OK;
 }
