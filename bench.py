@@ -102,16 +102,27 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(sp_factory, n_sample: int, seconds: float):
-    """The oracle (single thread, FP64) on a bounded sample of the workload: a
-    smaller box at the same state point, whole sweeps until `seconds` pass."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(sp_factory, n_sample: int, seconds: float, threads: int):
+    """The oracle (FP64) on a bounded sample of the workload: a smaller box at
+    the same state point, whole sweeps until `seconds` pass."""
     from oracle import pyoracle
-    from paper_1508_07077_amd import workloads as wl
 
     sp = sp_factory(n_sample)
     pos, _ = sp.initial_state()
     o = pyoracle.OracleSim(sp.n, sp.L, sp.seed)
     o.set_shape(pyoracle.SPHERE, sp.params)
+    o.set_threads(threads)
     o.set_fugacity(0.0, sp.d_dep, 0)
     o.set_moves(0.1)
     o.set_state(pos)
@@ -129,16 +140,31 @@ def cpu_baseline(sp_factory, n_sample: int, seconds: float):
         if time.perf_counter() - t0 >= seconds:
             break
     dt = time.perf_counter() - t0
+    return sp, trials / dt, resolved / dt, sweeps, dt
+
+
+def cpu_baseline(sp_factory, n_sample: int, seconds: float):
+    """The oracle as it is, timed on this host: with OpenMP threads over the
+    active cells of a phase on every core it may use (the same result as one
+    thread, bit for bit), and single-threaded beside it."""
+    threads = max(1, int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    threads = min(threads, os.cpu_count() or 1)
+    sp, m1, c1, s1, d1 = _oracle_rate(sp_factory, n_sample, 0.6 * seconds, 1)
+    _, mt, ct, st, dtt = _oracle_rate(sp_factory, n_sample, 0.4 * seconds, threads)
+    desc = (f"a {sp.n}-sphere box at the same state point (phi_c={sp.phi_c}, q={sp.q}, eta_r={sp.eta_r}, "
+            f"n_trial={sp.n_trial}, delta={sp.d_trans})")
     return {
-        "value": trials / dt,
+        "value": mt,
         "unit": "colloid trial moves/s",
-        "depletant_checks_per_s": resolved / dt,
-        "cores": 1,
+        "depletant_checks_per_s": ct,
+        "cores": threads,
         "kind": "oracle",
-        "sample": f"{sweeps} whole sweep(s) of a {sp.n}-sphere box at the same state point "
-                  f"(phi_c={sp.phi_c}, q={sp.q}, eta_r={sp.eta_r}, n_trial={sp.n_trial}, delta={sp.d_trans}), "
-                  f"single thread, {dt:.1f} s",
-        "host_cpus": os.cpu_count(),
+        "sample": f"{st} whole sweep(s) of {desc}, {threads} OpenMP threads over the active cells of a phase, "
+                  f"{dtt:.1f} s",
+        "single_thread": {"value": m1, "depletant_checks_per_s": c1, "cores": 1,
+                          "sample": f"{s1} whole sweep(s) of the same box, one thread, {d1:.1f} s"},
+        "nproc": os.cpu_count(),
+        "cpu_model": _cpu_model(),
     }
 
 

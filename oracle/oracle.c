@@ -1,6 +1,8 @@
 /*
- * oracle.c -- plain, single-threaded FP64 CPU oracle of the implicit-depletant
- * hard-particle Monte Carlo sweep (Glaser, Karas & Glotzer, arXiv:1508.07077).
+ * oracle.c -- plain FP64 CPU oracle of the implicit-depletant hard-particle
+ * Monte Carlo sweep (Glaser, Karas & Glotzer, arXiv:1508.07077).  Single
+ * threaded unless orc_set_threads asks for OpenMP threads over the active
+ * cells of a phase (the same result, bit for bit).
  *
  * TEST INFRASTRUCTURE ONLY: loaded by the test-suite, the smoke check and the
  * benchmark's CPU-baseline leg; never by the product path.  It shares no code
@@ -623,6 +625,8 @@ struct orc_sim {
     int trace_on;
     orc_record* trace;
     int64_t trace_n;
+    /* threads over the active cells of a phase (1: the plain serial loop) */
+    int threads;
     char err[256];
 };
 
@@ -649,6 +653,7 @@ orc_sim* orc_create(int64_t n, double box_L, uint64_t seed, uint32_t replica_id)
     s->cell_of = (int*)calloc((size_t)n, sizeof(int));
     s->members = (int*)calloc((size_t)n, sizeof(int));
     s->n_select = 1;
+    s->threads = 1;
     return s;
 }
 
@@ -764,6 +769,13 @@ int orc_get_state(const orc_sim* s, double* pos, double* quat, uint64_t* sweep_i
     if (quat)
         for (int a = 0; a < 4; ++a) memcpy(quat + (size_t)a * s->N, s->q[a], (size_t)s->N * sizeof(double));
     if (sweep_index) *sweep_index = s->sweep;
+    return 0;
+}
+
+int orc_set_threads(orc_sim* s, int threads)
+{
+    if (threads < 1) return fail(s, -1, "threads must be >= 1");
+    s->threads = threads;
     return 0;
 }
 
@@ -1116,6 +1128,75 @@ static int cheb(int a, int b, int n)
     return d < n - d ? d : n - d;
 }
 
+/* The trials of one active cell c in phase p, in round order (Sec. III.E:
+ * n_select n_c rounds, each selecting a member uniformly). */
+static void run_cell(orc_sim* s, int64_t c, int p, const double g[3], int* stidx, orc_counters* cnt)
+{
+    int n = s->n;
+    uint32_t sw = (uint32_t)s->sweep;
+    uint32_t w[4];
+    int offs[3], noff;
+    if (n == 2) {
+        offs[0] = 0;
+        offs[1] = 1;
+        noff = 2;
+    } else {
+        offs[0] = -1;
+        offs[1] = 0;
+        offs[2] = 1;
+        noff = 3;
+    }
+    int cx = (int)(c % n), cy = (int)((c / n) % n), cz = (int)(c / ((int64_t)n * n));
+    int nmem = s->cell_start[c + 1] - s->cell_start[c];
+    if (nmem == 0) return;
+    int ntr = s->n_select * nmem;
+    for (int t = 0; t < ntr; ++t) {
+        stream_t st = {{s->key[0], s->key[1]}, sw, (uint32_t)c, (uint32_t)t};
+        orc_record rec;
+        memset(&rec, 0, sizeof(rec));
+        draw(&st, P_SELECT, 0, w);
+        int jl = (int)pick(w[0], (uint32_t)nmem);
+        int64_t j = s->members[s->cell_start[c] + jl];
+        int rotate = s->sh.oriented && s->p_rot > 0.0 && u01(w[1]) < s->p_rot;
+        double xn[3], qn[4];
+        propose(s, j, &st, rotate, xn, qn);
+        int reason;
+        if (cell_of_point(s, xn, g) != (int)c) {
+            reason = ORC_REJ_CELL_EXIT;
+        } else {
+            /* stencil: de-duplicated neighbour cells, minus j */
+            int nst = 0;
+            for (int a = 0; a < noff; ++a)
+                for (int b = 0; b < noff; ++b)
+                    for (int d = 0; d < noff; ++d) {
+                        int ex = (cx + offs[d] + n) % n;
+                        int ey = (cy + offs[b] + n) % n;
+                        int ez = (cz + offs[a] + n) % n;
+                        int e = ex + n * (ey + n * ez);
+                        for (int q = s->cell_start[e]; q < s->cell_start[e + 1]; ++q)
+                            if (s->members[q] != j) stidx[nst++] = s->members[q];
+                    }
+            stencil_t stc = {stidx, nst};
+            reason = trial(s, j, xn, qn, &st, &stc, &rec, cnt);
+        }
+        if (reason == ORC_ACCEPT) {
+            for (int a = 0; a < 3; ++a) s->x[a][j] = xn[a];
+            for (int a = 0; a < 4; ++a) s->q[a][j] = qn[a];
+        }
+        count_reason(cnt, reason);
+        if (s->trace_on) {
+            rec.sweep = sw;
+            rec.cell = (uint32_t)c;
+            rec.t = (uint32_t)t;
+            rec.particle = (uint32_t)j;
+            rec.phase = (uint8_t)p;
+            rec.reason = (uint8_t)reason;
+            rec.rotation = (uint8_t)rotate;
+            s->trace[(int64_t)s->n_select * s->cell_start[c] + t] = rec;
+        }
+    }
+}
+
 /* One sweep.  target < 0: every cell.  target >= 0: only the cells whose
  * outcome can reach that cell's trials -- in phase q, the cells within
  * (periodic Chebyshev) distance p* - q of it, p* being its own phase -- so a
@@ -1166,18 +1247,6 @@ static void sweep_once(orc_sim* s, orc_counters* cnt, int64_t target)
     }
     free(fill);
 
-    int* stidx = (int*)malloc(sizeof(int) * (size_t)s->N);
-    int offs[3], noff;
-    if (n == 2) {
-        offs[0] = 0;
-        offs[1] = 1;
-        noff = 2;
-    } else {
-        offs[0] = -1;
-        offs[1] = 0;
-        offs[2] = 1;
-        noff = 3;
-    }
     int tx = 0, ty = 0, tz = 0, tphase = 7;
     if (target >= 0) {
         tx = (int)(target % n);
@@ -1187,9 +1256,12 @@ static void sweep_once(orc_sim* s, orc_counters* cnt, int64_t target)
         for (int p = 0; p < 8; ++p)
             if (perm[p] == tcol) tphase = p;
     }
+    int64_t* act = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nc > 0 ? nc : 1));
     for (int p = 0; p < 8; ++p) {
         int col = perm[p];
         if (target >= 0 && p > tphase) break;
+        /* the active cells of this phase, in ascending cell id */
+        int64_t nact = 0;
         for (int64_t c = 0; c < nc; ++c) {
             int cx = (int)(c % n), cy = (int)((c / n) % n), cz = (int)(c / ((int64_t)n * n));
             int ccol = (cx & 1) | ((cy & 1) << 1) | ((cz & 1) << 2);
@@ -1198,57 +1270,30 @@ static void sweep_once(orc_sim* s, orc_counters* cnt, int64_t target)
                 int reach = tphase - p;
                 if (cheb(cx, tx, n) > reach || cheb(cy, ty, n) > reach || cheb(cz, tz, n) > reach) continue;
             }
-            int nmem = s->cell_start[c + 1] - s->cell_start[c];
-            if (nmem == 0) continue;
-            int ntr = s->n_select * nmem;
-            for (int t = 0; t < ntr; ++t) {
-                stream_t st = {{s->key[0], s->key[1]}, sw, (uint32_t)c, (uint32_t)t};
-                orc_record rec;
-                memset(&rec, 0, sizeof(rec));
-                draw(&st, P_SELECT, 0, w);
-                int jl = (int)pick(w[0], (uint32_t)nmem);
-                int64_t j = s->members[s->cell_start[c] + jl];
-                int rotate = s->sh.oriented && s->p_rot > 0.0 && u01(w[1]) < s->p_rot;
-                double xn[3], qn[4];
-                propose(s, j, &st, rotate, xn, qn);
-                int reason;
-                if (cell_of_point(s, xn, g) != (int)c) {
-                    reason = ORC_REJ_CELL_EXIT;
-                } else {
-                    /* stencil: de-duplicated neighbour cells, minus j */
-                    int nst = 0;
-                    for (int a = 0; a < noff; ++a)
-                        for (int b = 0; b < noff; ++b)
-                            for (int d = 0; d < noff; ++d) {
-                                int ex = (cx + offs[d] + n) % n;
-                                int ey = (cy + offs[b] + n) % n;
-                                int ez = (cz + offs[a] + n) % n;
-                                int e = ex + n * (ey + n * ez);
-                                for (int q = s->cell_start[e]; q < s->cell_start[e + 1]; ++q)
-                                    if (s->members[q] != j) stidx[nst++] = s->members[q];
-                            }
-                    stencil_t stc = {stidx, nst};
-                    reason = trial(s, j, xn, qn, &st, &stc, &rec, cnt);
-                }
-                if (reason == ORC_ACCEPT) {
-                    for (int a = 0; a < 3; ++a) s->x[a][j] = xn[a];
-                    for (int a = 0; a < 4; ++a) s->q[a][j] = qn[a];
-                }
-                count_reason(cnt, reason);
-                if (s->trace_on) {
-                    rec.sweep = sw;
-                    rec.cell = (uint32_t)c;
-                    rec.t = (uint32_t)t;
-                    rec.particle = (uint32_t)j;
-                    rec.phase = (uint8_t)p;
-                    rec.reason = (uint8_t)reason;
-                    rec.rotation = (uint8_t)rotate;
-                    s->trace[(int64_t)s->n_select * s->cell_start[c] + t] = rec;
-                }
+            act[nact++] = c;
+        }
+        /* Cells of one colour share no stencil cell and each trial moves only a
+         * member of its own cell, so the cells of a phase may run in any order
+         * or at once (Sec. III.E); with threads > 1 they are spread over
+         * OpenMP threads, each with its own counters, summed afterwards
+         * (integer sums: the result is that of the serial loop). */
+#pragma omp parallel num_threads(s->threads) if (s->threads > 1)
+        {
+            int* stidx = (int*)malloc(sizeof(int) * (size_t)s->N);
+            orc_counters lc;
+            memset(&lc, 0, sizeof(lc));
+#pragma omp for schedule(dynamic, 16)
+            for (int64_t i = 0; i < nact; ++i) run_cell(s, act[i], p, g, stidx, &lc);
+#pragma omp critical
+            {
+                uint64_t* dst = (uint64_t*)cnt;
+                const uint64_t* src = (const uint64_t*)&lc;
+                for (size_t k = 0; k < sizeof(orc_counters) / sizeof(uint64_t); ++k) dst[k] += src[k];
             }
+            free(stidx);
         }
     }
-    free(stidx);
+    free(act);
     if (s->trace_on) s->trace_n = (int64_t)s->n_select * s->N;
     s->sweep++;
 }

@@ -107,6 +107,10 @@ int orc_set_insertion(orc_sim* s, int region);
 int orc_set_state(orc_sim* s, const double* pos_soa, const double* quat_soa, uint64_t sweep_index);
 int orc_get_state(const orc_sim* s, double* pos_soa, double* quat_soa, uint64_t* sweep_index);
 int orc_set_trace(orc_sim* s, int enable);
+/* OpenMP threads over the active cells of a phase (default 1: the serial
+ * loop).  The cells of a phase are independent, so the result is that of one
+ * thread, bit for bit. */
+int orc_set_threads(orc_sim* s, int threads);
 int orc_sweep(orc_sim* s, int n_sweeps, orc_counters* out);
 int orc_sweep_cone(orc_sim* s, int64_t target_cell, orc_counters* out);
 int orc_trace(const orc_sim* s, orc_record* buf, int64_t cap, int64_t* n_written);

@@ -80,7 +80,7 @@ def build(force: bool = False) -> str:
     if not force and os.path.exists(LIB_PATH) and os.path.getmtime(LIB_PATH) >= os.path.getmtime(src):
         return LIB_PATH
     cmd = [
-        "gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math",
+        "gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
         "-Wall", "-shared", "-fPIC", "-o", LIB_PATH + ".tmp", src, "-lm",
     ]
     subprocess.run(cmd, check=True)
@@ -108,6 +108,7 @@ def lib():
         L.orc_set_state.argtypes = [ctypes.c_void_p, c_d_p, c_d_p, ctypes.c_uint64]
         L.orc_get_state.argtypes = [ctypes.c_void_p, c_d_p, c_d_p, ctypes.POINTER(ctypes.c_uint64)]
         L.orc_set_trace.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.orc_set_threads.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.orc_sweep.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(_Counters)]
         L.orc_sweep_cone.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(_Counters)]
         L.orc_trace.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
@@ -237,6 +238,10 @@ class OracleSim:
         sw = ctypes.c_uint64(0)
         self._chk(lib().orc_get_state(self._h, _dp(pos), _dp(quat), ctypes.byref(sw)))
         return pos, quat, int(sw.value)
+
+    def set_threads(self, threads: int):
+        """OpenMP threads over the active cells of a phase (1 = serial)."""
+        self._chk(lib().orc_set_threads(self._h, int(threads)))
 
     def set_trace(self, enable: bool = True):
         self._chk(lib().orc_set_trace(self._h, 1 if enable else 0))

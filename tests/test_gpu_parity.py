@@ -43,6 +43,18 @@ def test_c1_spheres_trajectory(n_trial):
         assert tot["rej_cb_zero"] + tot["rej_cb_metropolis"] > 0
 
 
+@pytest.mark.parametrize("n_trial", [0, 4])
+def test_c1_spheres_whole_trajectory(n_trial):
+    """the 64-sphere workload's whole run: 1000 sweeps, every trial record and
+    the state after every sweep against the oracle (no tolerance)"""
+    sp = wl.c1_spheres_small(n_trial)
+    pos, _ = sp.initial_state()
+    g, o = make_pair(sp, pos)
+    tot, div = compare_sweeps(g, o, 1000)
+    assert div == 0
+    assert tot["trials"] == 1000 * sp.n and tot["accepts"] > 0
+
+
 def test_c3_shaped_box_cb():
     """spheres phi_c = 0.30, q = 0.10, eta_r = 0.30, n_trial = 4 (399 depletants per move)"""
     sp = wl.c3_spheres_large(n=3000, d_trans=0.003)
