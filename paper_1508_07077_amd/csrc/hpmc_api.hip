@@ -80,8 +80,8 @@ struct hpmc_sim {
     // handle, used in turn, each with the event after its last upload (a
     // buffer is rewritten only once its copy is done)
     static constexpr int kStages = 4;
-    Desc* batch_stage[kStages] = {};
-    size_t batch_stage_cap[kStages] = {};
+    unsigned char* batch_stage[kStages] = {};
+    size_t batch_stage_cap[kStages] = {};  // bytes
     hipEvent_t batch_up[kStages] = {};
     int batch_next = 0;
     unsigned long long* d_gather = nullptr;
@@ -304,9 +304,14 @@ Params make_params(const hpmc_sim* s)
     double rc2 = 2.0 * s->S.rcirc;
     int64_t list_cap = (s->n == 2) ? s->N : packing_bound(s, 3.0 * s->w + rc2);
     int gs = s->S.oriented ? 12 : 3;
-    int64_t geo_cap = s->S.oriented ? std::min<int64_t>(list_cap, 64) : std::min<int64_t>(list_cap, 512);
-    P.list_cap = static_cast<int>(list_cap);
-    P.geo_cap = static_cast<int>(geo_cap);
+    // Oriented shapes cache the stencil's positions and rotation matrices in
+    // LDS: 64 entries, which keeps two waves per SIMD resident; entries past the
+    // cache are read from HBM.  In a box of two cells per axis every colloid is
+    // in every stencil and a phase is one cell's serial chain of trials, so
+    // the whole box is cached (up to 512 colloids).
+    int64_t geo_cap = std::min<int64_t>(list_cap, 512);
+    if (s->S.oriented) geo_cap = std::min<int64_t>(list_cap, s->n == 2 ? 512 : 64);
+    const size_t lds_max = lds_limit();
     // A depletant point of B(x', R0) or a CB trial point of B(x, R0) can only
     // overlap a colloid whose reference point lies within reach of x'.
     const double reach = s->R0 + s->S.rcirc + 0.5 * s->d_dep + 1.7320508075688772 * s->d_trans * (1.0 + 1e-12) + 1e-9;
@@ -321,35 +326,49 @@ Params make_params(const hpmc_sim* s)
         P.off_geo = 0;
         P.off_cnt = static_cast<int>(2 * o);  // after the two stage buffers: the wave's counters
         P.wave_lds = static_cast<int>(2 * o + kNumCounters * 8);
+        P.list_cap = static_cast<int>(list_cap);
+        P.geo_cap = static_cast<int>(geo_cap);
         int wpb = s->tune_wpb ? s->tune_wpb : 4;
-        while (wpb > 1 && kTableLds + static_cast<size_t>(wpb) * P.wave_lds > 64 * 1024) wpb >>= 1;
+        while (wpb > 1 && kTableLds + static_cast<size_t>(wpb) * P.wave_lds > lds_max) wpb >>= 1;
         P.waves_per_block = wpb;
         P.chunk = s->tune_chunk ? s->tune_chunk : kChunk;
+        P.blk0 = 0;
+        P.nblk = phase_blocks(kSphere, P.active_cells, P.chunk, wpb, 0);
         return P;
     }
     // oriented shapes: the stencil list, the geometry cache and the per-trial
-    // close and reach lists (the cell's own records stay in HBM)
-    size_t off = align256(static_cast<size_t>(list_cap) * 4);
-    P.off_geo = static_cast<int>(off);
-    off = align256(off + static_cast<size_t>(geo_cap) * 8 * gs);
-    {
-        // A colloid whose reference point lies within 2 r_circ of the proposed
-        // one has its body inside the cube of side 6 r_circ around it; one in
-        // reach, inside the cube of side 2 reach + 2 r_circ.  Hard bodies are
-        // disjoint, so both counts obey the packing bound.
-        const double rc = s->S.rcirc;
-        P.close_cap = static_cast<int>(std::min<int64_t>(list_cap, packing_bound(s, 6.0 * rc)));
-        P.reach_cap = static_cast<int>(std::min<int64_t>(list_cap, packing_bound(s, 2.0 * reach + 2.0 * rc)));
+    // close and reach lists (the cell's own records stay in HBM); a cache that
+    // would not fit one wave's share of the LDS is halved
+    // A colloid whose reference point lies within 2 r_circ of the proposed one
+    // has its body inside the cube of side 6 r_circ around it; one in reach,
+    // inside the cube of side 2 reach + 2 r_circ.  Hard bodies are disjoint,
+    // so both counts obey the packing bound.
+    const double rc = s->S.rcirc;
+    P.close_cap = static_cast<int>(std::min<int64_t>(list_cap, packing_bound(s, 6.0 * rc)));
+    P.reach_cap = static_cast<int>(std::min<int64_t>(list_cap, packing_bound(s, 2.0 * reach + 2.0 * rc)));
+    size_t off = 0;
+    for (;;) {
+        off = align256(static_cast<size_t>(list_cap) * 4);
+        P.off_geo = static_cast<int>(off);
+        off = align256(off + static_cast<size_t>(geo_cap) * 8 * gs);
         P.off_close = static_cast<int>(off);
         off = align256(off + static_cast<size_t>(P.close_cap) * 4);
         P.off_reach = static_cast<int>(off);
         off = align256(off + static_cast<size_t>(P.reach_cap) * 4);
+        if (kTableLds + off <= lds_max || geo_cap <= 64) break;
+        geo_cap = std::max<int64_t>(64, geo_cap / 2);
     }
+    P.list_cap = static_cast<int>(list_cap);
+    P.geo_cap = static_cast<int>(geo_cap);
     P.wave_lds = static_cast<int>(off);
-    int wpb = s->tune_wpb ? s->tune_wpb : 4;
-    while (wpb > 1 && kTableLds + static_cast<size_t>(wpb) * off > 64 * 1024) wpb >>= 1;
+    // a large cache (dense boxes: few active cells, long serial chains) runs
+    // one wave per workgroup, so it holds a CU's LDS only as long as that wave
+    int wpb = s->tune_wpb ? s->tune_wpb : (geo_cap > 64 ? 1 : 4);
+    while (wpb > 1 && kTableLds + static_cast<size_t>(wpb) * off > lds_max) wpb >>= 1;
     P.waves_per_block = wpb;
     P.chunk = kChunk;
+    P.blk0 = 0;
+    P.nblk = phase_blocks(s->S.kind, P.active_cells, P.chunk, wpb, s->tune_waves ? s->tune_waves : kMaxWaves);
     return P;
 }
 
@@ -378,7 +397,10 @@ Group make_group(const Desc* d, const hpmc_sim* const* sims, int n)
     // small sphere boxes sweep in one workgroup per replica, many sweeps per launch
     g.lds_small = kTableLds + static_cast<size_t>(kSmallWaves) * wave_lds;
     g.small = g.kind == kSphere && g.maxActive <= kSmallMaxActive && g.maxN <= kSmallMaxN &&
-              g.lds_small <= 64 * 1024;
+              g.lds_small + kSmallStaticLds <= lds_limit();
+    // a group of one replica owns every block of its phase launches
+    g.brep = nullptr;
+    g.nblocks = phase_blocks(g.kind, g.maxActive, g.chunk, g.wpb, g.max_waves);
     return g;
 }
 
@@ -388,6 +410,8 @@ Desc make_desc(const hpmc_sim* s, int wpb, int chunk)
     d.P = make_params(s);
     d.P.waves_per_block = wpb;
     d.P.chunk = chunk;
+    d.P.blk0 = 0;
+    d.P.nblk = phase_blocks(s->S.kind, d.P.active_cells, chunk, wpb, s->tune_waves ? s->tune_waves : kMaxWaves);
     d.W = s->W;
     return d;
 }
@@ -440,7 +464,7 @@ int check_ready(hpmc_sim* s, bool need_state)
     if (s->ws_bytes < layout(s).total) return fail(s, HPMC_ENOMEM, "workspace too small for the current settings");
     if (need_state && !s->have_state) return fail(s, HPMC_ESTATE, "state not set");
     Params P = make_params(s);
-    if (kTableLds + static_cast<size_t>(P.waves_per_block) * P.wave_lds > 64 * 1024)
+    if (kTableLds + static_cast<size_t>(P.waves_per_block) * P.wave_lds > lds_limit())
         return fail(s, HPMC_ECAPACITY, "stencil too large for the LDS of one workgroup");
     if (s->sweep_dev_stale && s->have_state) {
         int r = set_sweep_dev(s);
@@ -506,7 +530,7 @@ int bind_static(hpmc_sim* s, Group& g, Work& W, unsigned long long** gather)
         return fail(s, HPMC_ENOMEM, "this handle needs " + std::to_string(need) + " bytes of scratch; the static "
                                     "scratch holds " + std::to_string(kStaticScratchBytes));
     Params P = make_params(s);
-    if (kTableLds + static_cast<size_t>(P.waves_per_block) * P.wave_lds > 64 * 1024)
+    if (kTableLds + static_cast<size_t>(P.waves_per_block) * P.wave_lds > lds_limit())
         return fail(s, HPMC_ECAPACITY, "stencil too large for the LDS of one workgroup");
     unsigned char* base = nullptr;
     int r = static_scratch(s, &base);
@@ -1076,28 +1100,45 @@ namespace {
 // ordered on the stream after the previous call's kernels, and a staging
 // buffer is rewritten only once its previous copy completed (with four in
 // turn, the host may enqueue that many calls ahead of the device).
-int upload_batch_descs(hpmc_sim* lead, Desc* d_all, const std::vector<Desc>& host, hipStream_t st)
+int upload_batch(hpmc_sim* lead, void* dst, const std::vector<unsigned char>& host, hipStream_t st)
 {
-    const size_t bytes = host.size() * sizeof(Desc);
+    const size_t bytes = host.size();
     const int k = lead->batch_next;
     lead->batch_next = (k + 1) % hpmc_sim::kStages;
     hipError_t e = hipSuccess;
     if (lead->batch_up[k]) e = hipEventSynchronize(lead->batch_up[k]);
-    if (e == hipSuccess && lead->batch_stage_cap[k] < host.size()) {
+    if (e == hipSuccess && lead->batch_stage_cap[k] < bytes) {
         if (lead->batch_stage[k]) e = hipHostFree(lead->batch_stage[k]);
         lead->batch_stage[k] = nullptr;
         lead->batch_stage_cap[k] = 0;
         if (e == hipSuccess)
             e = hipHostMalloc(reinterpret_cast<void**>(&lead->batch_stage[k]), bytes, hipHostMallocDefault);
-        if (e == hipSuccess) lead->batch_stage_cap[k] = host.size();
+        if (e == hipSuccess) lead->batch_stage_cap[k] = bytes;
     }
     if (e == hipSuccess && !lead->batch_up[k]) e = hipEventCreateWithFlags(&lead->batch_up[k], hipEventDisableTiming);
     if (e != hipSuccess) return hip_fail(lead, e, "batch descriptor staging");
     memcpy(lead->batch_stage[k], host.data(), bytes);
-    e = hipMemcpyAsync(d_all, lead->batch_stage[k], bytes, hipMemcpyHostToDevice, st);
+    e = hipMemcpyAsync(dst, lead->batch_stage[k], bytes, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipEventRecord(lead->batch_up[k], st);
     if (e != hipSuccess) return hip_fail(lead, e, "batch descriptor upload");
     return HPMC_OK;
+}
+
+// batch workspace: descriptors, then the block-to-replica map of the phase
+// launches (at most kMaxReplicaBlocks blocks per replica), then counters
+struct BatchLayout {
+    size_t desc, brep, gather, total;
+};
+
+BatchLayout batch_layout(int n_sims)
+{
+    BatchLayout l{};
+    const size_t n = static_cast<size_t>(n_sims);
+    l.desc = 0;
+    l.brep = align256(n * sizeof(Desc));
+    l.gather = l.brep + align256(n * kMaxReplicaBlocks * sizeof(int));
+    l.total = l.gather + align256(n * kCounterStride * 8);
+    return l;
 }
 
 }  // namespace
@@ -1105,8 +1146,7 @@ int upload_batch_descs(hpmc_sim* lead, Desc* d_all, const std::vector<Desc>& hos
 int hpmc_batch_workspace_bytes(int n_sims, size_t* bytes)
 {
     if (n_sims < 1 || !bytes) return HPMC_EINVAL;
-    *bytes = align256(static_cast<size_t>(n_sims) * sizeof(Desc)) +
-             align256(static_cast<size_t>(n_sims) * kCounterStride * 8);
+    *bytes = batch_layout(n_sims).total;
     return HPMC_OK;
 }
 
@@ -1129,27 +1169,46 @@ int hpmc_sweep_batch(hpmc_sim* const* sims, int n_sims, void* batch_ws, size_t b
     }
     hipStream_t st = sims[0]->stream;
     // replicas that share a shape kind, precision and insertion region share each launch
-    Desc* d_all = static_cast<Desc*>(batch_ws);
-    unsigned long long* d_gather = reinterpret_cast<unsigned long long*>(
-        static_cast<unsigned char*>(batch_ws) + align256(static_cast<size_t>(n_sims) * sizeof(Desc)));
-    std::vector<int> order;
-    // small sphere boxes form their own groups (one workgroup sweeps each)
+    const BatchLayout bl = batch_layout(n_sims);
+    unsigned char* base = static_cast<unsigned char*>(batch_ws);
+    Desc* d_all = reinterpret_cast<Desc*>(base + bl.desc);
+    int* d_brep = reinterpret_cast<int*>(base + bl.brep);
+    unsigned long long* d_gather = reinterpret_cast<unsigned long long*>(base + bl.gather);
+    std::vector<Params> par(static_cast<size_t>(n_sims));
+    for (int i = 0; i < n_sims; ++i) par[static_cast<size_t>(i)] = make_params(sims[i]);
+    // small sphere boxes form their own groups (one workgroup sweeps each);
+    // oriented boxes with a large geometry cache (dense: few active cells, long
+    // serial chains) too, so that their LDS does not lower everyone's occupancy
     auto small_ok = [&](int i) {
+        const Params& Pi = par[static_cast<size_t>(i)];
         if (sims[i]->S.kind != HPMC_SPHERE) return 0;
-        Params Pi = make_params(sims[i]);
         return (Pi.active_cells <= kSmallMaxActive && Pi.N <= kSmallMaxN &&
-                kTableLds + static_cast<size_t>(kSmallWaves) * Pi.wave_lds <= 64 * 1024)
+                kTableLds + static_cast<size_t>(kSmallWaves) * Pi.wave_lds + kSmallStaticLds <= lds_limit())
                    ? 1
                    : 0;
     };
+    auto dense = [&](int i) { return sims[i]->S.oriented && par[static_cast<size_t>(i)].geo_cap > 64 ? 1 : 0; };
     std::vector<int> cl(static_cast<size_t>(n_sims));
     for (int i = 0; i < n_sims; ++i)
-        cl[static_cast<size_t>(i)] = 8 * sims[i]->S.kind + 4 * small_ok(i) + 2 * sims[i]->precision + sims[i]->region;
+        cl[static_cast<size_t>(i)] =
+            16 * sims[i]->S.kind + 8 * dense(i) + 4 * small_ok(i) + 2 * sims[i]->precision + sims[i]->region;
     auto cls = [&](int i) { return cl[static_cast<size_t>(i)]; };
-    for (int k = 0; k < 24; ++k)
+    // within a group, the most crowded cells first: their blocks are dispatched
+    // first, since their serial chains of trials set the length of a phase
+    auto crowd = [&](int i) {
+        const Params& Pi = par[static_cast<size_t>(i)];
+        return static_cast<double>(Pi.N) / static_cast<double>(Pi.ncells);
+    };
+    std::vector<int> order;
+    for (int k = 0; k < 48; ++k) {
+        const size_t first = order.size();
         for (int i = 0; i < n_sims; ++i)
             if (cls(i) == k) order.push_back(i);
+        std::stable_sort(order.begin() + static_cast<std::ptrdiff_t>(first), order.end(),
+                         [&](int a, int b) { return crowd(a) > crowd(b); });
+    }
     std::vector<Desc> host(static_cast<size_t>(n_sims));
+    std::vector<int> brep;
     std::vector<Group> groups;
     for (size_t b = 0; b < order.size();) {
         size_t e = b;
@@ -1157,12 +1216,40 @@ int hpmc_sweep_batch(hpmc_sim* const* sims, int n_sims, void* batch_ws, size_t b
         std::vector<const hpmc_sim*> members;
         for (size_t q = b; q < e; ++q) members.push_back(sims[order[q]]);
         Group g = make_group(d_all + b, members.data(), static_cast<int>(members.size()));
-        for (size_t q = b; q < e; ++q) host[q] = make_desc(sims[order[q]], g.wpb, g.chunk);
+        // flat phase launch: each replica's own blocks, one after another
+        const size_t first_block = brep.size();
+        for (size_t q = b; q < e; ++q) {
+            Desc d = make_desc(sims[order[q]], g.wpb, g.chunk);
+            if (g.kind == kSphere) {
+                // a wave takes one chunk of cells: a large box takes larger chunks
+                while (d.P.nblk > kMaxReplicaBlocks && d.P.chunk < 64) {
+                    d.P.chunk = std::min(64, 2 * d.P.chunk);
+                    d.P.nblk = phase_blocks(kSphere, d.P.active_cells, d.P.chunk, g.wpb, 0);
+                }
+                if (d.P.nblk > kMaxReplicaBlocks)
+                    return fail(sims[0], HPMC_ECAPACITY, "replica " + std::to_string(order[q]) +
+                                                              " is too large for a batched sweep; sweep it alone");
+            }
+            // oriented shapes: the waves of a capped replica take several cells in turn
+            int nb = std::min(d.P.nblk, kMaxReplicaBlocks);
+            d.P.blk0 = static_cast<int>(brep.size() - first_block);
+            d.P.nblk = nb;
+            brep.insert(brep.end(), static_cast<size_t>(nb), static_cast<int>(q - b));
+            host[q] = d;
+        }
+        g.brep = d_brep + first_block;
+        g.nblocks = static_cast<int>(brep.size() - first_block);
         groups.push_back(g);
         b = e;
     }
-    int ru = upload_batch_descs(sims[0], d_all, host, st);
-    if (ru != HPMC_OK) return ru;
+    {
+        // descriptors and block map in one copy (they are adjacent)
+        std::vector<unsigned char> up(bl.brep + brep.size() * sizeof(int));
+        memcpy(up.data(), host.data(), host.size() * sizeof(Desc));
+        if (!brep.empty()) memcpy(up.data() + bl.brep, brep.data(), brep.size() * sizeof(int));
+        int ru = upload_batch(sims[0], base, up, st);
+        if (ru != HPMC_OK) return ru;
+    }
     hipError_t e = hipSuccess;
     for (const Group& g : groups)
         if (e == hipSuccess) e = launch_clear_counters(g, st);

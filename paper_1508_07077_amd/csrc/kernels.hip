@@ -20,12 +20,80 @@
 // and CB re-insertions of a blocking depletant run lane-per-trial.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "kernels.hpp"
 #include "rng.hpp"
 
 namespace hpmc {
 
 namespace {
+
+// Address spaces of the phase kernels' memory: LDS and global.  Pointers
+// typed with them compile to ds_* and global_* instructions instead of flat
+// ones, whose completion the wave could only await together (an LDS read
+// would then also wait for the next cell's records still streaming in).
+#define LAS __attribute__((address_space(3)))
+#define GAS __attribute__((address_space(1)))
+
+// the phase kernels' view of a replica's workspace, with global pointers
+struct WorkG {
+    const GAS int* cell_start;
+    GAS double4* rpos;
+    GAS double4* rquat;
+    const GAS double* F;
+    const GAS double* grid;
+    const GAS int* perm;
+    GAS unsigned long long* counters;
+    GAS int* flags;
+    GAS unsigned char* trace;
+    const GAS uint32_t* sweep_dev;
+};
+
+__device__ inline WorkG gview(const Work& W)
+{
+    WorkG g;
+    g.cell_start = (const GAS int*)W.cell_start;
+    g.rpos = (GAS double4*)W.rpos;
+    g.rquat = (GAS double4*)W.rquat;
+    g.F = (const GAS double*)W.F;
+    g.grid = (const GAS double*)W.grid;
+    g.perm = (const GAS int*)W.perm;
+    g.counters = (GAS unsigned long long*)W.counters;
+    g.flags = (GAS int*)W.flags;
+    g.trace = (GAS unsigned char*)W.trace;
+    g.sweep_dev = (const GAS uint32_t*)W.sweep_dev;
+    return g;
+}
+
+// 32-byte records in global memory (the vector types take no address-space
+// qualified references, so the four words are moved one by one; the compiler
+// merges them into wide loads and stores)
+__device__ inline double4 rd4(const GAS double4* p, size_t i)
+{
+    const GAS double* q = (const GAS double*)(p + i);
+    return make_double4(q[0], q[1], q[2], q[3]);
+}
+
+__device__ inline void wr4(GAS double4* p, size_t i, double4 v)
+{
+    GAS double* q = (GAS double*)(p + i);
+    q[0] = v.x;
+    q[1] = v.y;
+    q[2] = v.z;
+    q[3] = v.w;
+}
+
+// the same through plain (generic) pointers, for the kernels that use them
+__device__ inline double4 rd4(const double4* p, size_t i) { return p[i]; }
+__device__ inline void wr4(double4* p, size_t i, double4 v) { p[i] = v; }
+
+// LDS base of the dynamic shared memory
+__device__ inline LAS unsigned char* lds_base()
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    return (LAS unsigned char*)smem;
+}
 
 constexpr double kFar = 1.0e30;
 
@@ -209,15 +277,15 @@ __device__ inline bool ball4(Words w, double m[4])
 // that runs a cell reads or writes its members (neighbouring cells of the same
 // colour are two cells apart), so no other wave sees them change.
 struct WaveCtx {
-    int* list;          // stencil slots
-    double* geo;        // per-cell geometry cache: position (3) [+ R (9)] per entry
-    int* close;         // per trial: entries whose circumsphere meets the proposed pose's
-    int* reach;         // per trial: entries a depletant or CB trial point can overlap
+    LAS int* list;      // stencil slots
+    LAS double* geo;    // per-cell geometry cache: position (3) [+ R (9)] per entry
+    LAS int* close;     // per trial: entries whose circumsphere meets the proposed pose's
+    LAS int* reach;     // per trial: entries a depletant or CB trial point can overlap
     int start, nc, nst;
     int jslot;
     int jl;             // list index of the moved colloid (own members come first)
     int nr;             // entries in reach (all nst of them when rl is null)
-    const int* rl;      // reach, or null when the list overflowed its bound
+    const LAS int* rl;  // reach, or null when the list overflowed its bound
     Vec3 xn;
 };
 
@@ -232,41 +300,41 @@ struct Traits {
 // stencil entry i's reference point relative to the proposed position (the
 // moved colloid's own entry reads as far away)
 template <int KIND>
-__device__ inline Vec3 get_offset(const Params& P, const Work& W, const WaveCtx& c, int i)
+__device__ inline Vec3 get_offset(const Params& P, const WorkG& W, const WaveCtx& c, int i)
 {
     double4 p;
     if (i == c.jl) return v3(kFar, kFar, kFar);
     if (i < P.geo_cap) {
-        const double* g = c.geo + static_cast<size_t>(i) * Traits<KIND>::geo_stride;
+        const LAS double* g = c.geo + static_cast<size_t>(i) * Traits<KIND>::geo_stride;
         p = make_double4(g[0], g[1], g[2], 0.0);
     } else {
-        p = W.rpos[c.list[i]];
+        p = rd4(W.rpos, c.list[i]);
     }
     return v3(mi(P, p.x - c.xn.x), mi(P, p.y - c.xn.y), mi(P, p.z - c.xn.z));
 }
 
 // geometry of stencil entry i relative to the proposed position
 template <int KIND>
-__device__ inline void load_entry(const Params& P, const Work& W, const WaveCtx& c, int i, Vec3& D, Mat3& R)
+__device__ inline void load_entry(const Params& P, const WorkG& W, const WaveCtx& c, int i, Vec3& D, Mat3& R)
 {
     const int slot = c.list[i];
-    const double4 p = W.rpos[slot];
+    const double4 p = rd4(W.rpos, slot);
     if (slot == c.jslot) {
         D = v3(kFar, kFar, kFar);
     } else {
         D = v3(mi(P, p.x - c.xn.x), mi(P, p.y - c.xn.y), mi(P, p.z - c.xn.z));
     }
     if constexpr (Traits<KIND>::oriented) {
-        const double4 q = W.rquat[slot];
+        const double4 q = rd4(W.rquat, slot);
         R = quat_to_mat(q.x, q.y, q.z, q.w);
     }
 }
 
 template <int KIND>
-__device__ inline void get_entry(const Params& P, const Work& W, const WaveCtx& c, int i, Vec3& D, Mat3& R)
+__device__ inline void get_entry(const Params& P, const WorkG& W, const WaveCtx& c, int i, Vec3& D, Mat3& R)
 {
     if (i < P.geo_cap) {
-        const double* g = c.geo + static_cast<size_t>(i) * Traits<KIND>::geo_stride;
+        const LAS double* g = c.geo + static_cast<size_t>(i) * Traits<KIND>::geo_stride;
         D = (i == c.jl) ? v3(kFar, kFar, kFar) : v3(mi(P, g[0] - c.xn.x), mi(P, g[1] - c.xn.y), mi(P, g[2] - c.xn.z));
         if constexpr (Traits<KIND>::oriented) {
 #pragma unroll
@@ -337,7 +405,7 @@ __device__ inline bool dep_ov_g(const Params& P, Vec3 v, const Mat3& R, const Ma
 // wave-cooperative: does a depletant at offset e overlap any stencil colloid
 // (those in reach: no other can)?
 template <int KIND, bool F32 = false>
-__device__ inline bool stencil_hit_coop(const Params& P, const Work& W, const WaveCtx& c, Vec3 e, unsigned& fb)
+__device__ inline bool stencil_hit_coop(const Params& P, const WorkG& W, const WaveCtx& c, Vec3 e, unsigned& fb)
 {
     bool hit = false;
     for (int k = lane_id(); k < c.nr; k += 64) {
@@ -354,7 +422,7 @@ __device__ inline bool stencil_hit_coop(const Params& P, const Work& W, const Wa
 // per-lane: does the point p overlap any stencil colloid in reach?  (all lanes
 // read the same entry at the same time: LDS broadcast)
 template <int KIND>
-__device__ inline bool stencil_hit_lane(const Params& P, const Work& W, const WaveCtx& c, Vec3 p, bool active)
+__device__ inline bool stencil_hit_lane(const Params& P, const WorkG& W, const WaveCtx& c, Vec3 p, bool active)
 {
     bool hit = !active;
     for (int k = 0; k < c.nr; ++k) {
@@ -374,7 +442,7 @@ __device__ inline bool stencil_hit_lane(const Params& P, const Work& W, const Wa
 // ballot rank inside each half assigns the trial index, so one Philox pass
 // usually yields every trial.  Returns the valid counts W'_k and W_k.
 template <int KIND>
-__device__ inline void cb_weights(const Params& P, const Work& W, const WaveCtx& c, uint32_t C, uint32_t t,
+__device__ inline void cb_weights(const Params& P, const WorkG& W, const WaveCtx& c, uint32_t C, uint32_t t,
                                   uint32_t ks, Vec3 Dold, const Mat3& Rn, const Mat3& Ro, uint32_t& Wf, uint32_t& Wr)
 {
     const int lane = lane_id();
@@ -421,7 +489,8 @@ __device__ inline void cb_weights(const Params& P, const Work& W, const WaveCtx&
 }
 
 // smallest k with F[k] >= u, starting from the guide entry G[floor(256 u)]
-__device__ inline int poisson_guided(const double* F, const int* G, double u)
+template <typename FP, typename GP>
+__device__ inline int poisson_guided(FP F, GP G, double u)
 {
     int k = G[static_cast<int>(u * 256.0)];
     while (F[k] < u) ++k;
@@ -617,9 +686,9 @@ __global__ void gather_kernel(const Desc* __restrict__ D)
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= P.N) return;
     int i = W.order[s];
-    W.rpos[s] = make_double4(pos[i], pos[P.N + i], pos[2 * P.N + i], static_cast<double>(i));
+    wr4(W.rpos, s, make_double4(pos[i], pos[P.N + i], pos[2 * P.N + i], static_cast<double>(i)));
     if (P.S.oriented)
-        W.rquat[s] = make_double4(quat[i], quat[P.N + i], quat[2 * P.N + i], quat[3 * P.N + i]);
+        wr4(W.rquat, s, make_double4(quat[i], quat[P.N + i], quat[2 * P.N + i], quat[3 * P.N + i]));
 }
 
 // cell-ordered records back to the SoA state; the sweep counter advances here
@@ -631,13 +700,13 @@ __global__ void scatter_back_kernel(const Desc* __restrict__ D, int advance)
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (advance && s == 0) *W.sweep_dev = *W.sweep_dev + 1u;
     if (s >= P.N) return;
-    double4 r = W.rpos[s];
+    double4 r = rd4(W.rpos, s);
     int i = static_cast<int>(r.w);
     pos[i] = r.x;
     pos[P.N + i] = r.y;
     pos[2 * P.N + i] = r.z;
     if (P.S.oriented) {
-        double4 q = W.rquat[s];
+        double4 q = rd4(W.rquat, s);
         quat[i] = q.x;
         quat[P.N + i] = q.y;
         quat[2 * P.N + i] = q.z;
@@ -649,25 +718,25 @@ __global__ void scatter_back_kernel(const Desc* __restrict__ D, int advance)
 // one colour of the checkerboard: every active cell runs its trials
 // ---------------------------------------------------------------------------
 template <int KIND, bool F32>
-__device__ __forceinline__ void phase_body(const Params& P, const Work& W, int phase)
+__device__ __forceinline__ void phase_body(const Params& P, const WorkG& W, int phase, int lb, int nblk)
 {
     unsigned fb = 0;  // FP64 fallbacks of the guarded FP32 depletant tests (this lane)
-    extern __shared__ __align__(16) unsigned char smem[];
-    double* sF = reinterpret_cast<double*>(smem);
-    int* sG = reinterpret_cast<int*>(smem + kPoissonK * sizeof(double));
-    const int* gG = reinterpret_cast<const int*>(W.F + kPoissonK);
+    LAS unsigned char* smem = lds_base();
+    LAS double* sF = (LAS double*)smem;
+    LAS int* sG = (LAS int*)(smem + kPoissonK * sizeof(double));
+    const GAS int* gG = (const GAS int*)(W.F + kPoissonK);
     for (int i = threadIdx.x; i < kPoissonK; i += blockDim.x) sF[i] = W.F[i];
     for (int i = threadIdx.x; i < kGuide; i += blockDim.x) sG[i] = gG[i];
     __syncthreads();
 
     const int lane = lane_id();
     const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));  // wave-uniform
-    unsigned char* wbase = smem + kTableLds + static_cast<size_t>(wv) * P.wave_lds;
+    LAS unsigned char* wbase = smem + kTableLds + static_cast<size_t>(wv) * P.wave_lds;
     WaveCtx c;
-    c.list = reinterpret_cast<int*>(wbase);
-    c.geo = reinterpret_cast<double*>(wbase + P.off_geo);
-    c.close = reinterpret_cast<int*>(wbase + P.off_close);
-    c.reach = reinterpret_cast<int*>(wbase + P.off_reach);
+    c.list = (LAS int*)wbase;
+    c.geo = (LAS double*)(wbase + P.off_geo);
+    c.close = (LAS int*)(wbase + P.off_close);
+    c.reach = (LAS int*)(wbase + P.off_reach);
     constexpr int GS = Traits<KIND>::geo_stride;
     constexpr bool ORI = Traits<KIND>::oriented;
     static_assert(ORI, "spheres run phase_sphere_body");
@@ -677,8 +746,8 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
     for (int k = 0; k < kNumCounters; ++k) cnt[k] = 0ull;
 
     const int colour = W.perm[phase];
-    const int gw = blockIdx.x * P.waves_per_block + wv;
-    const int nwaves = gridDim.x * P.waves_per_block;
+    const int gw = lb * P.waves_per_block + wv;
+    const int nwaves = nblk * P.waves_per_block;
     const double g0 = W.grid[0], g1 = W.grid[1], g2 = W.grid[2];
     const NbOff nb = nb_offset(P.n);
 
@@ -700,7 +769,7 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
         int nst;
         int off = wave_excl_scan(ec, nst);
         if (nst > P.list_cap) {
-            if (lane == 0) atomicOr(W.flags, kFlagListOverflow);
+            if (lane == 0) __hip_atomic_fetch_or(W.flags, kFlagListOverflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             continue;
         }
         for (int k = 0; k < ec; ++k) c.list[off + k] = es + k;
@@ -712,13 +781,13 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
             const int ng = c.nst < P.geo_cap ? c.nst : P.geo_cap;
             for (int i = lane; i < ng; i += 64) {
                 const int slot = c.list[i];
-                const double4 pp = W.rpos[slot];
-                double* g = c.geo + static_cast<size_t>(i) * GS;
+                const double4 pp = rd4(W.rpos, slot);
+                LAS double* g = c.geo + static_cast<size_t>(i) * GS;
                 g[0] = pp.x;
                 g[1] = pp.y;
                 g[2] = pp.z;
                 if constexpr (ORI) {
-                    const double4 qq = W.rquat[slot];
+                    const double4 qq = rd4(W.rquat, slot);
                     Mat3 R = quat_to_mat(qq.x, qq.y, qq.z, qq.w);
 #pragma unroll
                     for (int k = 0; k < 9; ++k) g[3 + k] = R.m[k];
@@ -750,9 +819,9 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
             const bool rotate = ORI && P.p_rot > 0.0 && u01(sel1) < P.p_rot;
             c.jslot = c.start + jl;
             c.jl = jl;
-            const double4 pj = W.rpos[c.jslot];
+            const double4 pj = rd4(W.rpos, c.jslot);
             double4 qj = make_double4(1.0, 0.0, 0.0, 0.0);
-            if constexpr (ORI) qj = W.rquat[c.jslot];
+            if constexpr (ORI) qj = rd4(W.rquat, c.jslot);
             Vec3 xn = v3(pj.x, pj.y, pj.z);
             double qn[4] = {qj.x, qj.y, qj.z, qj.w};
             if (!rotate) {
@@ -841,7 +910,7 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
                 }
                 if (nlist) wave_sync();
                 // a list beyond its packing bound (impossible for disjoint bodies) falls back to every entry
-                const int* cl_list = (nlist && ncl <= P.close_cap) ? c.close : nullptr;
+                const LAS int* cl_list = (nlist && ncl <= P.close_cap) ? c.close : nullptr;
                 const int n_close = cl_list ? ncl : c.nst;
                 c.rl = (nlist && nrc <= P.reach_cap) ? c.reach : nullptr;
                 c.nr = c.rl ? nrc : c.nst;
@@ -969,10 +1038,10 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
             }
             // --- accept / commit / record ---------------------------------------
             if (o.reason == 0 && lane == 0) {
-                W.rpos[c.jslot] = make_double4(xn.x, xn.y, xn.z, pj.w);
-                if constexpr (ORI) W.rquat[c.jslot] = make_double4(qn[0], qn[1], qn[2], qn[3]);
+                wr4(W.rpos, c.jslot, make_double4(xn.x, xn.y, xn.z, pj.w));
+                if constexpr (ORI) wr4(W.rquat, c.jslot, make_double4(qn[0], qn[1], qn[2], qn[3]));
                 if (jl < P.geo_cap) {
-                    double* g = c.geo + static_cast<size_t>(jl) * GS;
+                    LAS double* g = c.geo + static_cast<size_t>(jl) * GS;
                     g[0] = xn.x;
                     g[1] = xn.y;
                     g[2] = xn.z;
@@ -997,8 +1066,7 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
             cnt[cCbTrials] += o.cbt;
             cnt[cNearContact] += o.near ? 1 : 0;
             if (P.trace && lane == 0) {
-                uint32_t* r = reinterpret_cast<uint32_t*>(static_cast<unsigned char*>(W.trace) +
-                                                          (static_cast<size_t>(P.n_select) * c.start + t) * 40);
+                GAS uint32_t* r = (GAS uint32_t*)(W.trace + (static_cast<size_t>(P.n_select) * c.start + t) * 40);
                 r[0] = P.sweep;
                 r[1] = static_cast<uint32_t>(C);
                 r[2] = static_cast<uint32_t>(t);
@@ -1015,10 +1083,10 @@ __device__ __forceinline__ void phase_body(const Params& P, const Work& W, int p
     }
     cnt[cFp64Fallbacks] += static_cast<unsigned long long>(wave_sum(static_cast<int>(fb)));
     if (lane == 0) {
-        unsigned long long* dst = W.counters + static_cast<size_t>(gw % kCounterCopies) * kCounterStride;
+        GAS unsigned long long* dst = W.counters + static_cast<size_t>(gw % kCounterCopies) * kCounterStride;
 #pragma unroll
         for (int k = 0; k < kNumCounters; ++k)
-            if (cnt[k]) atomicAdd(dst + k, cnt[k]);
+            if (cnt[k]) __hip_atomic_fetch_add(dst + k, cnt[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -1056,9 +1124,9 @@ __device__ inline bool sphere_in(const Params& P, Vec3 a, Vec3 b, bool active, u
 }
 
 struct SphereStage {
-    int* list;      // stencil slots (list_cap)
-    double* recA;   // entry i: (x, y) at [2i, 2i + 1]
-    double* recB;   // entry i: (z, particle index) at [2i, 2i + 1]
+    LAS int* list;     // stencil slots (list_cap)
+    LAS double* recA;  // entry i: (x, y) at [2i, 2i + 1]
+    LAS double* recB;  // entry i: (z, particle index) at [2i, 2i + 1]
 };
 
 __device__ inline double4 stage_rec(const SphereStage& sb, int i)
@@ -1068,7 +1136,7 @@ __device__ inline double4 stage_rec(const SphereStage& sb, int i)
 
 // neighbour-cell ranges of cell C at (cx, cy, cz): a lane with nb.on holds
 // the range of its neighbour (lane 0: C itself)
-__device__ inline void stencil_ranges(const Params& P, const Work& W, const NbOff& nb, int C, int cx, int cy, int cz,
+__device__ inline void stencil_ranges(const Params& P, const WorkG& W, const NbOff& nb, int C, int cx, int cy, int cz,
                                       int& es, int& ec)
 {
     es = 0;
@@ -1082,7 +1150,7 @@ __device__ inline void stencil_ranges(const Params& P, const Work& W, const NbOf
 
 // write the stencil list of a cell and start the direct loads of its first
 // kStage records into LDS; returns the stencil size (or -1 on overflow)
-__device__ inline int stage_issue(const Params& P, const Work& W, const SphereStage& sb, int es, int ec)
+__device__ inline int stage_issue(const Params& P, const WorkG& W, const SphereStage& sb, int es, int ec)
 {
     const int lane = lane_id();
     int nst;
@@ -1091,9 +1159,9 @@ __device__ inline int stage_issue(const Params& P, const Work& W, const SphereSt
     for (int k = 0; k < ec; ++k) sb.list[off + k] = es + k;
     wave_sync();
     if (lane < nst && lane < kStage) {
-        const char* g = reinterpret_cast<const char*>(W.rpos + sb.list[lane]);
-        __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)(sb.recA), 16, 0, 0);
-        __builtin_amdgcn_global_load_lds(g + 16, (__attribute__((address_space(3))) void*)(sb.recB), 16, 0, 0);
+        const GAS char* g = (const GAS char*)(W.rpos + sb.list[lane]);
+        __builtin_amdgcn_global_load_lds((const GAS void*)g, (LAS void*)sb.recA, 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((const GAS void*)(g + 16), (LAS void*)sb.recB, 16, 0, 0);
     }
     return nst;
 }
@@ -1102,7 +1170,7 @@ __device__ inline int stage_issue(const Params& P, const Work& W, const SphereSt
 // The staged entries (lane i of Dreg holds entry i's offset) are taken from
 // rmask, the entries in reach of the CB regions, read across lanes; entries
 // beyond the stage from the records.
-__device__ inline bool sphere_hit_lane(const Params& P, const Work& W, const SphereStage& sb, int nst, int jent,
+__device__ inline bool sphere_hit_lane(const Params& P, const WorkG& W, const SphereStage& sb, int nst, int jent,
                                        Vec3 xn, unsigned long long rmask, Vec3 Dreg, Vec3 p, bool active)
 {
     bool hit = !active;
@@ -1114,7 +1182,7 @@ __device__ inline bool sphere_hit_lane(const Params& P, const Work& W, const Sph
     for (int i = kStage; i < nst; ++i) {
         if (__ballot(!hit) == 0ull) break;
         if (i == jent) continue;
-        double4 r = W.rpos[sb.list[i]];
+        double4 r = rd4(W.rpos, sb.list[i]);
         Vec3 D = v3(mi(P, r.x - xn.x), mi(P, r.y - xn.y), mi(P, r.z - xn.z));
         if (!hit) hit = dot(p - D, p - D) < P.S.R0sq;
     }
@@ -1122,35 +1190,37 @@ __device__ inline bool sphere_hit_lane(const Params& P, const Work& W, const Sph
 }
 
 // Poisson table and its guide into the workgroup's LDS (before any phase body)
-__device__ inline void load_table(const Work& W, unsigned char* smem)
+__device__ inline void load_table(const WorkG& W, LAS unsigned char* smem)
 {
-    double* sF = reinterpret_cast<double*>(smem);
-    int* sG = reinterpret_cast<int*>(smem + kPoissonK * sizeof(double));
-    const int* gG = reinterpret_cast<const int*>(W.F + kPoissonK);
+    LAS double* sF = (LAS double*)smem;
+    LAS int* sG = (LAS int*)(smem + kPoissonK * sizeof(double));
+    const GAS int* gG = (const GAS int*)(W.F + kPoissonK);
     for (int i = threadIdx.x; i < kPoissonK; i += blockDim.x) sF[i] = W.F[i];
     for (int i = threadIdx.x; i < kGuide; i += blockDim.x) sG[i] = gG[i];
 }
 
 // One wave's share of a phase: the chunk gw of active cells (P.chunk cells).
 template <bool F32, bool SHELL>
-__device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W, int phase, int gw)
+__device__ __forceinline__ void phase_sphere_body(const Params& P, const WorkG& W, int phase, int gw)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
-    double* sF = reinterpret_cast<double*>(smem);
-    int* sG = reinterpret_cast<int*>(smem + kPoissonK * sizeof(double));
+    LAS unsigned char* smem = lds_base();
+    LAS double* sF = (LAS double*)smem;
+    LAS int* sG = (LAS int*)(smem + kPoissonK * sizeof(double));
 
     const int lane = lane_id();
     const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));  // wave-uniform
-    unsigned char* wbase = smem + kTableLds + static_cast<size_t>(wv) * P.wave_lds;
+    LAS unsigned char* wbase = smem + kTableLds + static_cast<size_t>(wv) * P.wave_lds;
     auto stage_buf = [&](int b) {
-        unsigned char* q = wbase + static_cast<size_t>(b) * (P.off_cnt / 2);
-        return SphereStage{reinterpret_cast<int*>(q), reinterpret_cast<double*>(q + P.off_rec_a),
-                           reinterpret_cast<double*>(q + P.off_rec_b)};
+        LAS unsigned char* q = wbase + static_cast<size_t>(b) * (P.off_cnt / 2);
+        return SphereStage{(LAS int*)q, (LAS double*)(q + P.off_rec_a), (LAS double*)(q + P.off_rec_b)};
     };
 
     // the wave's counters live in its LDS (uniform values, no registers); lane
     // 0 adds to them without waiting for the result
-    unsigned long long* wcnt = reinterpret_cast<unsigned long long*>(wbase + P.off_cnt);
+    LAS unsigned long long* wcnt = (LAS unsigned long long*)(wbase + P.off_cnt);
+    auto wadd = [&](int k, unsigned long long v) {
+        __hip_atomic_fetch_add(wcnt + k, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
     if (lane < kNumCounters) wcnt[lane] = 0ull;
     unsigned fallbacks = 0;  // FP64 fallbacks of the guarded FP32 tests (this lane)
 
@@ -1217,7 +1287,7 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
             ranges_of(kn2, es, ec);
         }
         if (nst < 0) {
-            if (lane == 0) atomicOr(W.flags, kFlagListOverflow);
+            if (lane == 0) __hip_atomic_fetch_or(W.flags, kFlagListOverflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             const int ntr = P.n_select * nc;
             for (int t = 0; t < ntr; ++t) {
@@ -1236,7 +1306,7 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
                 Words w = draw(P, static_cast<uint32_t>(C), static_cast<uint32_t>(t), purpose, index);
                 const int jl = static_cast<int>(pick(rdlane_u(w.w0, 0), static_cast<uint32_t>(nc)));
                 // own members are entries 0 .. nc-1: staged, or (past the stage) in HBM
-                const double4 pj = jl < kStage ? stage_rec(S0, jl) : W.rpos[start + jl];
+                const double4 pj = jl < kStage ? stage_rec(S0, jl) : rd4(W.rpos, start + jl);
                 Vec3 xn;
                 {
                     uint32_t tw0 = rdlane_u(w.w0, 1), tw1 = rdlane_u(w.w1, 1), tw2 = rdlane_u(w.w2, 1);
@@ -1265,11 +1335,11 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
                     bool hit = dot(Dreg, Dreg) < P.S.dsq;
                     for (int i = kStage + lane; i < nst; i += 64) {
                         if (i == jl) continue;  // the moved colloid itself (a member past the stage)
-                        double4 r = W.rpos[S0.list[i]];
+                        double4 r = rd4(W.rpos, S0.list[i]);
                         Vec3 D = v3(mi(P, r.x - xn.x), mi(P, r.y - xn.y), mi(P, r.z - xn.z));
                         hit = hit || dot(D, D) < P.S.dsq;
                     }
-                    if (lane == 0) atomicAdd(&wcnt[cOverlapChecks], static_cast<unsigned long long>(nst - 1));
+                    if (lane == 0) wadd(cOverlapChecks, static_cast<unsigned long long>(nst - 1));
                     // staged entries a CB trial point can reach (the moved colloid's lane holds kFar)
                     const unsigned long long rmask = __ballot(dot(Dreg, Dreg) < P.reach_sq);
                     if (__ballot(hit) != 0ull) {
@@ -1329,7 +1399,7 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
                                 bool h = sphere_in<F32>(P, es3, Dreg, true, fallbacks);
                                 for (int i = kStage + lane; i < nst; i += 64) {
                                     if (i == jl) continue;
-                                    double4 r = W.rpos[S0.list[i]];
+                                    double4 r = rd4(W.rpos, S0.list[i]);
                                     Vec3 D = v3(mi(P, r.x - xn.x), mi(P, r.y - xn.y), mi(P, r.z - xn.z));
                                     h = h || dot(es3 - D, es3 - D) < P.S.R0sq;
                                 }
@@ -1405,20 +1475,19 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
                     } else {
                         // a member past the stage: its record is updated in place (only this
                         // wave reads the cell's members during the phase)
-                        W.rpos[start + jl] = make_double4(xn.x, xn.y, xn.z, pj.w);
+                        wr4(W.rpos, start + jl, make_double4(xn.x, xn.y, xn.z, pj.w));
                     }
                 }
                 wave_sync();
                 if (lane == 0) {
-                    atomicAdd(&wcnt[cTrials], 1ull);
-                    atomicAdd(&wcnt[cAccepts + o.reason], 1ull);  // reasons 0..5 in counter order
-                    if (o.n_dep) atomicAdd(&wcnt[cDrawn], static_cast<unsigned long long>(o.n_dep));
-                    if (o.resolved) atomicAdd(&wcnt[cResolved], static_cast<unsigned long long>(o.resolved));
-                    if (o.cbt) atomicAdd(&wcnt[cCbTrials], static_cast<unsigned long long>(o.cbt));
+                    wadd(cTrials, 1ull);
+                    wadd(cAccepts + o.reason, 1ull);  // reasons 0..5 in counter order
+                    if (o.n_dep) wadd(cDrawn, static_cast<unsigned long long>(o.n_dep));
+                    if (o.resolved) wadd(cResolved, static_cast<unsigned long long>(o.resolved));
+                    if (o.cbt) wadd(cCbTrials, static_cast<unsigned long long>(o.cbt));
                 }
                 if (P.trace && lane == 0) {
-                    uint32_t* r = reinterpret_cast<uint32_t*>(static_cast<unsigned char*>(W.trace) +
-                                                              (static_cast<size_t>(P.n_select) * start + t) * 40);
+                    GAS uint32_t* r = (GAS uint32_t*)(W.trace + (static_cast<size_t>(P.n_select) * start + t) * 40);
                     r[0] = P.sweep;
                     r[1] = static_cast<uint32_t>(C);
                     r[2] = static_cast<uint32_t>(t);
@@ -1432,7 +1501,7 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
                 }
             }
             // staged own-cell records back to HBM
-            for (int i = lane; i < nc && i < kStage; i += 64) W.rpos[start + i] = stage_rec(S0, i);
+            for (int i = lane; i < nc && i < kStage; i += 64) wr4(W.rpos, start + i, stage_rec(S0, i));
         }
         kc = kn;
         kn = kn2;
@@ -1442,15 +1511,15 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
     (void)Rnone;
     if constexpr (F32) {
         const int fb = wave_sum(static_cast<int>(fallbacks));
-        if (lane == 0 && fb) atomicAdd(&wcnt[cFp64Fallbacks], static_cast<unsigned long long>(fb));
+        if (lane == 0 && fb) wadd(cFp64Fallbacks, static_cast<unsigned long long>(fb));
     }
     wave_sync();
     if (lane == 0) {
-        unsigned long long* dst = W.counters + static_cast<size_t>(gw % kCounterCopies) * kCounterStride;
+        GAS unsigned long long* dst = W.counters + static_cast<size_t>(gw % kCounterCopies) * kCounterStride;
 #pragma unroll
         for (int k = 0; k < kNumCounters; ++k) {
             const unsigned long long v = wcnt[k];
-            if (v) atomicAdd(dst + k, v);
+            if (v) __hip_atomic_fetch_add(dst + k, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
@@ -1460,20 +1529,28 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const Work& W
 #endif
 // F32: depletant tests in FP32 with the FP64 guard band (precision HPMC_FP32_GUARDED);
 // SHELL: depletants in the shell region
+// Phase launches are flat: the blocks of every replica of a group follow each
+// other (brep[b] names block b's replica; null for a launch of one replica),
+// so a launch holds only blocks with work, and every block serves one replica
+// (its Poisson table and LDS layout).
+#define HPMC_PHASE_REPLICA(D, brep)                                             \
+    const int rep_ = (brep) ? (brep)[blockIdx.x] : 0;                           \
+    Params P = (D)[rep_].P;                                                     \
+    const WorkG W = gview((D)[rep_].W);                                         \
+    const int lb = static_cast<int>(blockIdx.x) - P.blk0; /* block in the replica */ \
+    const int nb = P.nblk
+
 template <bool F32, bool SHELL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HPMC_SPHERE_WAVES_PER_EU, 8))) void
-phase_sphere_kernel(const Desc* __restrict__ D, int phase)
+phase_sphere_kernel(const Desc* __restrict__ D, const int* __restrict__ brep, int phase)
 {
-    Params P = D[blockIdx.y].P;
-    const Work W = D[blockIdx.y].W;
+    HPMC_PHASE_REPLICA(D, brep);
     P.sweep = *W.sweep_dev;
-    extern __shared__ __align__(16) unsigned char smem[];
-    load_table(W, smem);
+    load_table(W, lds_base());
     __syncthreads();
-    // one box: XCD-aware chunk order; a batch keeps the dispatch order, since
-    // its small replicas have work only in their first blocks
-    const int b = gridDim.y == 1 ? xcd_block(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x))
-                                 : static_cast<int>(blockIdx.x);
+    // one box: XCD-aware chunk order; a batch keeps the dispatch order.  Every
+    // wave takes one chunk of P.chunk active cells (the launch covers them all).
+    const int b = brep ? lb : xcd_block(lb, nb);
     phase_sphere_body<F32, SHELL>(P, W, phase,
                                   b * P.waves_per_block +
                                       __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6)));
@@ -1512,7 +1589,7 @@ __global__ __launch_bounds__(64 * kSmallWaves) void sweep_small_kernel(const Des
 {
     Params P = D[blockIdx.y].P;
     const Work W = D[blockIdx.y].W;
-    extern __shared__ __align__(16) unsigned char smem[];
+    const WorkG WG = gview(W);
     __shared__ int s_wsum[kSmallWaves];
     __shared__ int s_carry;
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -1521,7 +1598,7 @@ __global__ __launch_bounds__(64 * kSmallWaves) void sweep_small_kernel(const Des
     // spread the active cells of a phase over the waves (trials of one cell are serial)
     P.chunk = (P.active_cells + kSmallWaves - 1) / kSmallWaves;
     if (P.chunk > 64) P.chunk = 64;
-    load_table(W, smem);
+    load_table(WG, lds_base());
     for (int sw = 0; sw < n_sweeps; ++sw) {
         P.sweep = sweep0 + static_cast<uint32_t>(sw);
         if (tid == 0) grid_setup(P, W);
@@ -1571,16 +1648,16 @@ __global__ __launch_bounds__(64 * kSmallWaves) void sweep_small_kernel(const Des
         __syncthreads();
         for (int q = tid; q < P.N; q += nt) {
             int i = W.order[q];
-            W.rpos[q] = make_double4(W.pos[i], W.pos[P.N + i], W.pos[2 * P.N + i], static_cast<double>(i));
+            wr4(W.rpos, q, make_double4(W.pos[i], W.pos[P.N + i], W.pos[2 * P.N + i], static_cast<double>(i)));
         }
         __syncthreads();
         for (int phase = 0; phase < 8; ++phase) {
             for (int gw = wv; gw * P.chunk < P.active_cells; gw += kSmallWaves)
-                phase_sphere_body<F32, SHELL>(P, W, phase, gw);
+                phase_sphere_body<F32, SHELL>(P, WG, phase, gw);
             __syncthreads();
         }
         for (int q = tid; q < P.N; q += nt) {
-            double4 r = W.rpos[q];
+            double4 r = rd4(W.rpos, q);
             int i = static_cast<int>(r.w);
             W.pos[i] = r.x;
             W.pos[P.N + i] = r.y;
@@ -1593,12 +1670,12 @@ __global__ __launch_bounds__(64 * kSmallWaves) void sweep_small_kernel(const Des
 
 // F32: depletant predicates in FP32 with the FP64 guard band
 template <int KIND, bool F32>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F32 ? 2 : 1, 8))) void phase_oriented_kernel(const Desc* __restrict__ D, int phase)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F32 ? 2 : 1, 8))) void phase_oriented_kernel(
+    const Desc* __restrict__ D, const int* __restrict__ brep, int phase)
 {
-    Params P = D[blockIdx.y].P;
-    const Work W = D[blockIdx.y].W;
+    HPMC_PHASE_REPLICA(D, brep);
     P.sweep = *W.sweep_dev;
-    phase_body<KIND, F32>(P, W, phase);
+    phase_body<KIND, F32>(P, W, phase, lb, nb);
 }
 
 __global__ void reduce_counters_kernel(const Desc* __restrict__ D)
@@ -1617,11 +1694,11 @@ __global__ void overlap_count_kernel(const Desc* __restrict__ D)
     HPMC_REPLICA(D);
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= P.N) return;
-    double4 a = W.rpos[s];
+    double4 a = rd4(W.rpos, s);
     int ia = static_cast<int>(a.w);
     Mat3 RA, RB;
     if (P.S.oriented) {
-        double4 q = W.rquat[s];
+        double4 q = rd4(W.rquat, s);
         RA = quat_to_mat(q.x, q.y, q.z, q.w);
     }
     int cx = cell_coord(P, a.x, 0.0), cy = cell_coord(P, a.y, 0.0), cz = cell_coord(P, a.z, 0.0);
@@ -1636,12 +1713,12 @@ __global__ void overlap_count_kernel(const Desc* __restrict__ D)
         }
         int e = (cx + dx + P.n) % P.n + P.n * ((cy + dy + P.n) % P.n + P.n * ((cz + dz + P.n) % P.n));
         for (int q = W.cell_start[e]; q < W.cell_start[e + 1]; ++q) {
-            double4 b = W.rpos[q];
+            double4 b = rd4(W.rpos, q);
             int ib = static_cast<int>(b.w);
             if (ib <= ia) continue;
             Vec3 d = v3(mi(P, b.x - a.x), mi(P, b.y - a.y), mi(P, b.z - a.z));
             if (P.S.oriented) {
-                double4 qb = W.rquat[q];
+                double4 qb = rd4(W.rquat, q);
                 RB = quat_to_mat(qb.x, qb.y, qb.z, qb.w);
             }
             if (pair_overlap(P.S, d, RA, RB).overlap) cntv++;
@@ -1679,7 +1756,7 @@ __global__ __launch_bounds__(256) void gr_kernel(const Desc* __restrict__ D, int
     __syncthreads();
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s < P.N) {
-        double4 a = W.rpos[s];
+        double4 a = rd4(W.rpos, s);
         int ia = static_cast<int>(a.w);
         int cx = cell_coord(P, a.x, 0.0), cy = cell_coord(P, a.y, 0.0), cz = cell_coord(P, a.z, 0.0);
         double inv_dr = static_cast<double>(n_bins) / r_max;
@@ -1694,7 +1771,7 @@ __global__ __launch_bounds__(256) void gr_kernel(const Desc* __restrict__ D, int
                     int ez = (nz == P.n) ? dz : wrap_cell(cz + fz + dz, P.n);
                     int e = ex + P.n * (ey + P.n * ez);
                     for (int q = W.cell_start[e]; q < W.cell_start[e + 1]; ++q) {
-                        double4 b = W.rpos[q];
+                        double4 b = rd4(W.rpos, q);
                         if (static_cast<int>(b.w) <= ia) continue;
                         Vec3 d = v3(mi(P, b.x - a.x), mi(P, b.y - a.y), mi(P, b.z - a.z));
                         double r2 = dot(d, d);
@@ -1734,12 +1811,12 @@ __global__ __launch_bounds__(256) void free_volume_kernel(const Desc* __restrict
             }
             int e = wrap_cell(cx + dx, P.n) + P.n * (wrap_cell(cy + dy, P.n) + P.n * wrap_cell(cz + dz, P.n));
             for (int q = W.cell_start[e]; q < W.cell_start[e + 1] && !hit; ++q) {
-                double4 b = W.rpos[q];
+                double4 b = rd4(W.rpos, q);
                 Vec3 v = v3(mi(P, X - b.x), mi(P, Y - b.y), mi(P, Z - b.z));
                 if (scale != 1.0) v = v3(v.x * scale, v.y * scale, v.z * scale);
                 Mat3 R;
                 if (P.S.oriented) {
-                    double4 qq = W.rquat[q];
+                    double4 qq = rd4(W.rquat, q);
                     R = quat_to_mat(qq.x, qq.y, qq.z, qq.w);
                 }
                 hit = dep_overlap(P.S, v, R);
@@ -1786,11 +1863,11 @@ __global__ __launch_bounds__(128) void sdf_kernel(const Desc* __restrict__ D, in
     int* cand = cand_lds + threadIdx.x * kSdfCand;
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = s < P.N;
-    double4 a = live ? W.rpos[s] : make_double4(0.0, 0.0, 0.0, -1.0);
+    double4 a = live ? rd4(W.rpos, s) : make_double4(0.0, 0.0, 0.0, -1.0);
     int ia = static_cast<int>(a.w);
     Mat3 RA, RB;
     if (P.S.oriented && live) {
-        double4 q = W.rquat[s];
+        double4 q = rd4(W.rquat, s);
         RA = quat_to_mat(q.x, q.y, q.z, q.w);
     }
     int cx = cell_coord(P, a.x, 0.0), cy = cell_coord(P, a.y, 0.0), cz = cell_coord(P, a.z, 0.0);
@@ -1809,7 +1886,7 @@ __global__ __launch_bounds__(128) void sdf_kernel(const Desc* __restrict__ D, in
                 int ez = (nz == P.n) ? dz : wrap_cell(cz + fz + dz, P.n);
                 int e = ex + P.n * (ey + P.n * ez);
                 for (int q = W.cell_start[e]; q < W.cell_start[e + 1]; ++q) {
-                    double4 b = W.rpos[q];
+                    double4 b = rd4(W.rpos, q);
                     if (static_cast<int>(b.w) == ia) continue;
                     Vec3 d = v3(mi(P, b.x - a.x), mi(P, b.y - a.y), mi(P, b.z - a.z));
                     double dd = dot(d, d);
@@ -1822,7 +1899,7 @@ __global__ __launch_bounds__(128) void sdf_kernel(const Desc* __restrict__ D, in
                         continue;
                     }
                     // keep the pair if it overlaps at the largest compression
-                    double4 qb = W.rquat[q];
+                    double4 qb = rd4(W.rquat, q);
                     RB = quat_to_mat(qb.x, qb.y, qb.z, qb.w);
                     double f = 1.0 - x_max;
                     Vec3 dm = v3(d.x * f, d.y * f, d.z * f);
@@ -1843,9 +1920,9 @@ __global__ __launch_bounds__(128) void sdf_kernel(const Desc* __restrict__ D, in
     // does not overlap at the current minimum cannot lower it (monotonicity).
     for (int c = 0; c < ncand; ++c) {
         int q = cand[c];
-        double4 b = W.rpos[q];
+        double4 b = rd4(W.rpos, q);
         Vec3 d = v3(mi(P, b.x - a.x), mi(P, b.y - a.y), mi(P, b.z - a.z));
-        double4 qb = W.rquat[q];
+        double4 qb = rd4(W.rquat, q);
         RB = quat_to_mat(qb.x, qb.y, qb.z, qb.w);
         if (xmin < x_max) {
             double f = 1.0 - xmin;
@@ -1897,33 +1974,77 @@ hipError_t launch_build_cells(const Group& g, bool with_grid, hipStream_t stream
     return hipGetLastError();
 }
 
+int phase_blocks(int kind, int active, int chunk, int wpb, int max_waves)
+{
+    int waves = kind == kSphere ? blocks_for(active, chunk) : (active < max_waves ? active : max_waves);
+    return blocks_for(waves, wpb);
+}
+
+namespace {
+// The phase kernels may use every byte of LDS the device gives a workgroup
+// (less their static LDS).  A refusal leaves the default limit; the error it
+// leaves behind is cleared so that no later launch check reports it.
+template <typename K>
+void raise_lds(K kernel, size_t bytes)
+{
+    hipFuncAttributes a{};
+    const void* f = reinterpret_cast<const void*>(kernel);
+    if (hipFuncGetAttributes(&a, f) == hipSuccess && a.sharedSizeBytes < bytes)
+        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  static_cast<int>(bytes - a.sharedSizeBytes));
+    (void)hipGetLastError();
+}
+}  // namespace
+
+size_t lds_limit()
+{
+    static std::once_flag once[64];
+    static size_t limit[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 64 * 1024;
+    std::call_once(once[dev], [dev]() {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v < 65536)
+            v = 65536;
+        limit[dev] = static_cast<size_t>(v);
+        raise_lds(phase_sphere_kernel<false, false>, limit[dev]);
+        raise_lds(phase_sphere_kernel<false, true>, limit[dev]);
+        raise_lds(phase_sphere_kernel<true, false>, limit[dev]);
+        raise_lds(phase_sphere_kernel<true, true>, limit[dev]);
+        raise_lds(phase_oriented_kernel<kHemisphere, false>, limit[dev]);
+        raise_lds(phase_oriented_kernel<kHemisphere, true>, limit[dev]);
+        raise_lds(phase_oriented_kernel<kDiscoid, false>, limit[dev]);
+        raise_lds(phase_oriented_kernel<kDiscoid, true>, limit[dev]);
+        raise_lds(sweep_small_kernel<false, false>, limit[dev]);
+        raise_lds(sweep_small_kernel<false, true>, limit[dev]);
+        raise_lds(sweep_small_kernel<true, false>, limit[dev]);
+        raise_lds(sweep_small_kernel<true, true>, limit[dev]);
+    });
+    return limit[dev];
+}
+
 hipError_t launch_phase(const Group& g, int phase, hipStream_t stream)
 {
-    const int R = g.nrep;
-    dim3 bs(64 * g.wpb);
+    dim3 bs(64 * g.wpb), grid(g.nblocks);
     if (g.kind == kSphere) {
-        int waves = blocks_for(g.maxActive, g.chunk);
-        dim3 grid(blocks_for(waves, g.wpb), R);
         if (g.precision == 1 && g.shell)
-            hipLaunchKernelGGL((phase_sphere_kernel<true, true>), grid, bs, g.lds, stream, g.d, phase);
+            hipLaunchKernelGGL((phase_sphere_kernel<true, true>), grid, bs, g.lds, stream, g.d, g.brep, phase);
         else if (g.precision == 1)
-            hipLaunchKernelGGL((phase_sphere_kernel<true, false>), grid, bs, g.lds, stream, g.d, phase);
+            hipLaunchKernelGGL((phase_sphere_kernel<true, false>), grid, bs, g.lds, stream, g.d, g.brep, phase);
         else if (g.shell)
-            hipLaunchKernelGGL((phase_sphere_kernel<false, true>), grid, bs, g.lds, stream, g.d, phase);
+            hipLaunchKernelGGL((phase_sphere_kernel<false, true>), grid, bs, g.lds, stream, g.d, g.brep, phase);
         else
-            hipLaunchKernelGGL((phase_sphere_kernel<false, false>), grid, bs, g.lds, stream, g.d, phase);
+            hipLaunchKernelGGL((phase_sphere_kernel<false, false>), grid, bs, g.lds, stream, g.d, g.brep, phase);
     } else {
-        int waves = g.maxActive < g.max_waves ? g.maxActive : g.max_waves;
-        if (R > 1 && waves > 512) waves = 512;
-        dim3 grid(blocks_for(waves, g.wpb), R);
         if (g.kind == kHemisphere && g.precision == 1)
-            hipLaunchKernelGGL((phase_oriented_kernel<kHemisphere, true>), grid, bs, g.lds, stream, g.d, phase);
+            hipLaunchKernelGGL((phase_oriented_kernel<kHemisphere, true>), grid, bs, g.lds, stream, g.d, g.brep, phase);
         else if (g.kind == kHemisphere)
-            hipLaunchKernelGGL((phase_oriented_kernel<kHemisphere, false>), grid, bs, g.lds, stream, g.d, phase);
+            hipLaunchKernelGGL((phase_oriented_kernel<kHemisphere, false>), grid, bs, g.lds, stream, g.d, g.brep,
+                               phase);
         else if (g.precision == 1)
-            hipLaunchKernelGGL((phase_oriented_kernel<kDiscoid, true>), grid, bs, g.lds, stream, g.d, phase);
+            hipLaunchKernelGGL((phase_oriented_kernel<kDiscoid, true>), grid, bs, g.lds, stream, g.d, g.brep, phase);
         else
-            hipLaunchKernelGGL((phase_oriented_kernel<kDiscoid, false>), grid, bs, g.lds, stream, g.d, phase);
+            hipLaunchKernelGGL((phase_oriented_kernel<kDiscoid, false>), grid, bs, g.lds, stream, g.d, g.brep, phase);
     }
     return hipGetLastError();
 }

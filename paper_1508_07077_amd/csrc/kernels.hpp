@@ -68,6 +68,8 @@ struct Params {
     int waves_per_block;
     int chunk;          // spheres: active cells per wave (1..64)
     int active_cells;   // h^3
+    // the phase launch: this replica's blocks are blk0 .. blk0 + nblk - 1 of the grid
+    int blk0, nblk;
 };
 
 // device workspace carved from the caller's buffer
@@ -101,6 +103,8 @@ struct Desc {
 // host-side launch shape of a group of replicas of one shape kind
 struct Group {
     const Desc* d;  // device array of nrep descriptors
+    const int* brep;  // phase launches: replica of each block (null: one replica owns every block)
+    int nblocks;      // phase launches: blocks of the grid
     int nrep;
     int kind;
     int precision;  // 0 FP64, 1 FP32 with the FP64 guard band (sphere depletant tests)
@@ -128,11 +132,19 @@ hipError_t launch_gr(const Group& g, const Params& P, const Work& W, int n_bins,
 hipError_t launch_free_volume(const Group& g, int64_t n_probe, uint32_t seq, double scale, int slot,
                               hipStream_t stream);
 hipError_t launch_sdf(const Group& g, const Params& P, const Work& W, int n_bins, double x_max, hipStream_t stream);
+// largest dynamic LDS of one workgroup on the current device (bytes); raises
+// the phase kernels' LDS limit to it on first use
+size_t lds_limit();
+// phase blocks one replica needs: spheres, chunks of `chunk` active cells per
+// wave; oriented shapes, one wave per active cell up to max_waves
+int phase_blocks(int kind, int active, int chunk, int wpb, int max_waves);
 
 constexpr int kChunk = 16;  // default active cells per wave of the sphere phase kernel
+constexpr int kMaxReplicaBlocks = 1024;  // phase blocks of one replica in a batched launch (waves loop over more)
 constexpr int kMaxWaves = 256 * 32;  // default wave count of the oriented phase launch
 constexpr int kSmallMaxActive = 32;  // spheres with at most this many active cells per phase and
 constexpr int kSmallMaxN = 8192;     // at most this many particles sweep in one workgroup
 constexpr int kSmallWaves = 8;       // waves of that workgroup
+constexpr size_t kSmallStaticLds = 256;  // that workgroup's static LDS (scan partials), rounded up
 
 }  // namespace hpmc
