@@ -48,17 +48,31 @@ def shell_ops_per_check(R0: float, r_i: float) -> float:
     return 76.0 / acc + 14.0
 
 
-# Calibrated VALU work per resolved depletant of the sphere phase kernel (ball
-# region), from rocprofv3 SQ_INSTS_VALU: (VALU instructions per move with
-# depletants - without) x 64 lanes / resolved depletants per move, i.e. all the
-# work the depletants cause (placement, classification, Poisson count,
-# survivor walk, CB passes), none of the per-move selection/proposal/stencil
-# work.  HBM bytes per launch from two rocprofv3 passes (FETCH_SIZE,
-# WRITE_SIZE) scaled by the same counters over a plain 256 MiB device copy.
-# Both hold only for the kernel sources with this digest.
-PROFILED_KERNEL_DIGEST = "fecfdc0df97d214e"
-CALIBRATED_OPS_PER_CHECK = 228.60
-PROFILED_TRAFFIC_BYTES = {"ball": 70860997, "shell": 70972806}
+# Active VALU lane-instructions of the phase kernels, from rocprofv3 counters
+# (SQ_INSTS_VALU x 64 x VALUUtilization per launch) of the kernel sources with
+# the digest below, split as the method's work is: a_dep per resolved
+# depletant check (timed launches with depletants minus launches of the same
+# state at zero fugacity) plus b_move per trial move (the zero-fugacity
+# launches).  achieved = (a_dep x resolved checks + b_move x moves) per launch
+# / the launch's duration, timed live with HIP events; frac = achieved / peak
+# is therefore the share of the VALU's lane-instruction slots the kernel keeps
+# busy with active lanes (rocprofv3 VALUBusy x VALUUtilization).  The HBM bytes
+# per launch are FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the factors a plain
+# 256 MiB device copy reads off the same counters).
+PROFILED_KERNEL_DIGEST = "36915d0909f6f47f"
+PROFILE = {
+    # 1,048,576 spheres, ball region, 212.05 resolved checks per move
+    "sphere": {"a_dep": 172.09, "b_move": 15854.4, "valu_instr_per_move": 1207.4, "valu_busy": 66.86,
+               "valu_utilization": 67.74, "traffic_bytes_per_launch": 67611067},
+    # 16,384 hemispheres at eta_r 0.4, 72.31 resolved checks per move
+    "hemisphere": {"a_dep": 393.34, "b_move": 32966.0, "valu_instr_per_move": 2142.3, "valu_busy": 12.35,
+                   "valu_utilization": 44.79, "traffic_bytes_per_launch": 4455252},
+    # 256 swept-disk replicas, both launch groups of a phase, 56.50 resolved checks per move
+    "discoid": {"a_dep": 483.28, "b_move": 29808.9, "valu_instr_per_move": 2428.0,
+                "valu_busy": {"replicas of two cells per axis": 0.85, "the others": 43.87},
+                "valu_utilization": {"replicas of two cells per axis": 34.11, "the others": 36.80},
+                "traffic_bytes_per_phase": 93871679},
+}
 
 
 def kernel_digest() -> str:
@@ -95,6 +109,8 @@ def parse():
                     help="c2: comma-separated reservoir packing fractions eta_r to run")
     ap.add_argument("--no-fp32", dest="fp32", action="store_false",
                     help="c2, c3: skip the FP32-guarded companion run")
+    ap.add_argument("--no-companion", dest="companion", action="store_false",
+                    help="c3: skip the other-insertion-region companion run (profiling)")
     ap.add_argument("--no-alone", dest="alone", action="store_false",
                     help="c4: skip the one-replica-at-a-time comparison")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -217,26 +233,26 @@ def main():
     minimal_ops = ALGO_OPS_PER_CHECK if region == hp.V0_BALL else \
         shell_ops_per_check(R0, max(0.0, R0 - math.sqrt(3.0) * sp.d_trans))
     profiled = kernel_digest() == PROFILED_KERNEL_DIGEST
-    # the per-unit figure: calibrated from the profiled kernel (ball region), else the minimal count
-    ops_per_check = CALIBRATED_OPS_PER_CHECK if (profiled and region == hp.V0_BALL) else minimal_ops
-    per_launch = tot["depletants_resolved"] / launches
-    achieved = ops_per_check * per_launch / avg_phase_s
-    achieved_minimal = minimal_ops * per_launch / avg_phase_s
+    per_launch_checks = tot["depletants_resolved"] / launches
+    per_launch_moves = tot["trials"] / launches
+    achieved_minimal = minimal_ops * per_launch_checks / avg_phase_s
     # the same state point with the other insertion region, timed right after
-    other = hp.V0_BALL if region == hp.V0_SHELL else hp.V0_SHELL
-    sim.set_insertion(other)
-    sim.ensure_workspace()
-    tot2, lat2, _, dt2 = _timed_sweeps(torch, sim, args.steps, args.warmup)
-    companion = {
-        "insertion_region": "shell" if other == hp.V0_SHELL else "ball",
-        "moves_per_s": tot2["trials"] / dt2,
-        "depletant_checks_per_s": tot2["depletants_resolved"] / dt2,
-        "ms_per_step": dt2 * 1e3 / args.steps,
-        "p50_ms": float(np.percentile(lat2, 50)),
-        "p99_ms": float(np.percentile(lat2, 99)),
-        "acceptance": tot2["accepts"] / tot2["trials"],
-        "depletants_per_move": tot2["depletants_drawn"] / tot2["trials"],
-    }
+    companion = None
+    if args.companion:
+        other = hp.V0_BALL if region == hp.V0_SHELL else hp.V0_SHELL
+        sim.set_insertion(other)
+        sim.ensure_workspace()
+        tot2, lat2, _, dt2 = _timed_sweeps(torch, sim, args.steps, args.warmup)
+        companion = {
+            "insertion_region": "shell" if other == hp.V0_SHELL else "ball",
+            "moves_per_s": tot2["trials"] / dt2,
+            "depletant_checks_per_s": tot2["depletants_resolved"] / dt2,
+            "ms_per_step": dt2 * 1e3 / args.steps,
+            "p50_ms": float(np.percentile(lat2, 50)),
+            "p99_ms": float(np.percentile(lat2, 99)),
+            "acceptance": tot2["accepts"] / tot2["trials"],
+            "depletants_per_move": tot2["depletants_drawn"] / tot2["trials"],
+        }
     # FP32 geometry with the FP64 guard band, same state point and region as the headline
     fp32 = None
     if args.fp32:
@@ -269,22 +285,10 @@ def main():
         "acceptance": tot["accepts"] / tot["trials"],
         "depletants_per_move": tot["depletants_drawn"] / tot["trials"],
         "resolved_per_move": tot["depletants_resolved"] / tot["trials"],
-        "roofline": {
-            "bound": "alu",
-            "kernel": "phase_kernel<sphere>",
-            "achieved": achieved / 1e12,
-            "peak": VALU_PEAK_LANE_OPS / 1e12,
-            "unit": "T VALU lane-instr/s",
-            "frac": achieved / VALU_PEAK_LANE_OPS,
-            "traffic": PROFILED_TRAFFIC_BYTES[args.v0] if profiled else None,
-            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "avg_launch_ms": avg_phase_s * 1e3,
-            "ops_per_check": ops_per_check,
-            "ops_source": "SQ_INSTS_VALU calibration of this kernel" if ops_per_check == CALIBRATED_OPS_PER_CHECK
-                          else "minimal instruction count",
-            "frac_minimal": achieved_minimal / VALU_PEAK_LANE_OPS,
-            "ops_per_check_minimal": minimal_ops,
-        },
+        "roofline": _roofline("sphere", profiled and region == hp.V0_BALL, per_launch_checks, per_launch_moves,
+                              avg_phase_s, "phase_sphere_kernel (one launch per checkerboard colour)",
+                              extra={"frac_minimal": achieved_minimal / VALU_PEAK_LANE_OPS,
+                                     "ops_per_check_minimal": minimal_ops}),
         "other_insertion_region": companion,
         "fp32_guarded": fp32,
         "launch_tuning": tuning,
@@ -293,6 +297,34 @@ def main():
         line["cpu_baseline"] = cpu_baseline(lambda n: wl.c3_spheres_large(n=n, d_trans=sp.d_trans), args.cpu_n,
                                             args.cpu_seconds)
     print(json.dumps(line), flush=True)
+
+
+def _roofline(shape, profiled, checks, moves, seconds, kernel, extra=None, per="launch"):
+    """The roofline object of the phase kernel: active VALU lane-instructions
+    of `checks` resolved depletant checks and `moves` trial moves done in
+    `seconds` (one launch, or one batched sweep), against the VALU peak."""
+    prof = PROFILE[shape]
+    d = {"bound": "alu", "kernel": kernel, "peak": VALU_PEAK_LANE_OPS / 1e12, "unit": "T VALU lane-instr/s",
+         "avg_launch_ms" if per == "launch" else "avg_sweep_ms": seconds * 1e3}
+    if profiled:
+        ops = prof["a_dep"] * checks + prof["b_move"] * moves
+        d.update({"achieved": ops / seconds / 1e12, "frac": ops / seconds / VALU_PEAK_LANE_OPS,
+                  "basis": "active VALU lane-instructions (rocprofv3 SQ_INSTS_VALU x 64 x VALUUtilization of this "
+                           f"kernel): {prof['a_dep']} per resolved depletant check + {prof['b_move']} per trial move",
+                  "valu_busy_pct": prof["valu_busy"], "valu_utilization_pct": prof["valu_utilization"],
+                  "valu_instr_per_move": prof["valu_instr_per_move"]})
+        if "traffic_bytes_per_launch" in prof:
+            d["traffic"] = prof["traffic_bytes_per_launch"]
+            d["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)"
+        else:
+            d["traffic"] = prof["traffic_bytes_per_phase"]
+            d["traffic_unit"] = "bytes per phase, both launch groups (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)"
+    else:
+        d.update({"achieved": None, "frac": None, "traffic": None,
+                  "basis": "kernel sources differ from the profiled ones: no calibration"})
+    if extra:
+        d.update(extra)
+    return d
 
 
 def _fp32_companion(hp, torch, sp, sim, region, args, launches):
@@ -428,9 +460,11 @@ def bench_c2(args):
     from paper_1508_07077_amd import workloads as wl
 
     per = {}
+    roofs = {}
     moves = checks = secs = 0.0
     lat = []
     fp32 = {}
+    profiled = kernel_digest() == PROFILED_KERNEL_DIGEST
     for eta in [float(x) for x in args.eta.split(",")]:
         sp = wl.c2_hemispheres(eta)
         sim = _make(hp, sp)
@@ -446,10 +480,15 @@ def bench_c2(args):
             lat.append((time.perf_counter() - ts) * 1e3)
             tot = c if tot is None else {k: tot[k] + c[k] for k in tot}
         dt = time.perf_counter() - t0
+        launches = 8 * args.steps
+        roof = _roofline("hemisphere", profiled, tot["depletants_resolved"] / launches, tot["trials"] / launches,
+                         tot["phase_kernel_ms"] / 1e3 / launches, "phase_oriented_kernel<hemisphere>")
         per[str(eta)] = {"moves_per_s": tot["trials"] / dt, "depletant_checks_per_s": tot["depletants_resolved"] / dt,
                          "acceptance": tot["accepts"] / tot["trials"], "ms_per_sweep": dt * 1e3 / args.steps,
                          "z_p": sp.z_p, "delta": sp.d_trans, "near_contact_trials": tot["near_contact"],
-                         "launch_tuning": tuning}
+                         "launch_tuning": tuning, "roofline_frac": roof["frac"],
+                         "avg_launch_ms": roof["avg_launch_ms"]}
+        roofs[str(eta)] = roof
         moves += tot["trials"]
         checks += tot["depletants_resolved"]
         secs += dt
@@ -471,7 +510,9 @@ def bench_c2(args):
     d = _line(moves / secs, {"depletants_resolved": checks, "accepts": 1, "trials": 1}, secs, 4 * args.steps,
               3, "hemispheres N=16384 phi_c=0.20 q=0.15 eta_r in {0.1,0.2,0.3,0.4}, p_rot=0.5, FP64",
               {"per_eta_r": per, "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-               "fp32_guarded_per_eta_r": fp32})
+               "fp32_guarded_per_eta_r": fp32,
+               # the state point with the most depletant work (the profiled one when it ran)
+               "roofline": roofs.get("0.4", roofs[max(roofs)]) if roofs else None})
     d.pop("acceptance")
     return d
 
@@ -502,14 +543,20 @@ def bench_c4(args):
     torch.cuda.synchronize()
     lat = []
     tot = None
+    dev_ms = 0.0
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ts = time.perf_counter()
         cs = b.sweep(1, counters=True)
         lat.append((time.perf_counter() - ts) * 1e3)
-        c = {k: sum(x[k] for x in cs) for k in cs[0]}
+        dev_ms += cs[0]["sweep_ms"]
+        c = {k: sum(x[k] for x in cs) for k in cs[0] if k != "sweep_ms"}
         tot = c if tot is None else {k: tot[k] + c[k] for k in tot}
     dt = time.perf_counter() - t0
+    roof = _roofline("discoid", kernel_digest() == PROFILED_KERNEL_DIGEST, tot["depletants_resolved"] / args.steps,
+                     tot["trials"] / args.steps, dev_ms / 1e3 / args.steps,
+                     "phase_oriented_kernel<discoid> (two launch groups per phase; the time is the whole batched "
+                     "sweep on the device, cell lists included)", per="sweep")
     alone = None
     # the same replicas swept one at a time (each handle's own launches), for comparison
     for x in (sims if args.alone else []):
@@ -528,7 +575,7 @@ def bench_c4(args):
                  f"256 swept-disk replicas, N={sum(s.n for s in sps)} in total (128..8192 each), "
                  "phi_c U[0.05,0.45], eta_r U[0,0.5], q=0.2, one launch per kernel for all replicas",
                  {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                  "replicas": len(sps), "launch_tuning": tuning, "one_at_a_time": alone})
+                  "replicas": len(sps), "launch_tuning": tuning, "one_at_a_time": alone, "roofline": roof})
 
 
 def bench_c5(args):

@@ -250,7 +250,7 @@ typedef struct hpmc_tuning {
 int hpmc_set_tuning(hpmc_sim* sim, const hpmc_tuning* tuning);
 
 /* Autotuner: time candidate launch shapes (spheres: cells per wave in
- * {4, 8, 16, 32, 64} x waves per block in {1, 2, 4}; oriented shapes: waves
+ * {4, 8, 10, 12, 16, 32, 64} x waves per block in {1, 2, 4}; oriented shapes: waves
  * per block x wave count in {1024 .. 32768}) on a copy of the current state,
  * `sweeps` timed sweeps each after one untimed, keep the fastest, and report
  * it in *out (may be NULL).  The handle's state and sweep index are left as
@@ -272,7 +272,9 @@ int hpmc_batch_workspace_bytes(int n_sims, size_t* bytes);
  * off.  batch_ws: device scratch of hpmc_batch_workspace_bytes(n_sims); the
  * descriptors are copied into it on the stream from pinned host staging
  * buffers of sims[0], so the call does not wait for the device unless out is
- * given.  out: NULL or n_sims counter records (synchronises).  Errors: EINVAL,
+ * given.  out: NULL or n_sims counter records (synchronises); their
+ * sweep_ms is the device time of the whole batched call, the same in every
+ * record, and phase_kernel_ms is 0.  Errors: EINVAL,
  * ESTATE, ENOMEM, EHIP, ECAPACITY (as for hpmc_sweep, per replica). */
 int hpmc_sweep_batch(hpmc_sim* const* sims, int n_sims, void* batch_ws, size_t bytes, int n_sweeps,
                      hpmc_counters* out);

@@ -344,4 +344,7 @@ class Batch:
             raise HpmcError(rc, f"sweep_batch: {msg.decode() if msg else ''}")
         if not counters:
             return None
-        return [{f: int(getattr(c, f)) for f in COUNTERS} for c in out]
+        res = [{f: int(getattr(c, f)) for f in COUNTERS} for c in out]
+        for d, c in zip(res, out):
+            d["sweep_ms"] = float(c.sweep_ms)
+        return res

@@ -1020,7 +1020,7 @@ int hpmc_autotune(hpmc_sim* s, void* scratch, size_t bytes, int sweeps, hpmc_tun
     // candidates
     std::vector<hpmc_tuning> cand;
     if (!s->S.oriented) {
-        for (int c : {16, 4, 8, 32, 64})
+        for (int c : {16, 4, 8, 10, 12, 32, 64})
             for (int w : {4, 2, 1}) cand.push_back(hpmc_tuning{c, w, 0, 0, 0.0, 0.0});
     } else {
         for (int m : {kMaxWaves, 1024, 2048, 4096, 16384, 32768})
@@ -1251,9 +1251,16 @@ int hpmc_sweep_batch(hpmc_sim* const* sims, int n_sims, void* batch_ws, size_t b
         if (ru != HPMC_OK) return ru;
     }
     hipError_t e = hipSuccess;
+    if (out) {
+        int re = ensure_events(sims[0], 2);
+        if (re != HPMC_OK) return re;
+    }
     for (const Group& g : groups)
         if (e == hipSuccess) e = launch_clear_counters(g, st);
+    // with counters: the device time of the sweeps of every group, on the lead stream
+    if (e == hipSuccess && out) e = hipEventRecord(sims[0]->events[0], st);
     if (e == hipSuccess) e = run_sweeps(sims[0], groups, n_sweeps, st);
+    if (e == hipSuccess && out) e = hipEventRecord(sims[0]->events[1], st);
     if (e != hipSuccess) return hip_fail(sims[0], e, "batched sweep launch");
     for (int i = 0; i < n_sims; ++i) sims[i]->sweep += static_cast<uint64_t>(n_sweeps);
     if (out) {
@@ -1267,9 +1274,13 @@ int hpmc_sweep_batch(hpmc_sim* const* sims, int n_sims, void* batch_ws, size_t b
             e = hipMemcpyAsync(hc.data(), d_gather, hc.size() * 8, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(sims[0], e, "batched counters");
+        float all = 0.0f;
+        e = hipEventElapsedTime(&all, sims[0]->events[0], sims[0]->events[1]);
+        if (e != hipSuccess) return hip_fail(sims[0], e, "hipEventElapsedTime");
         int r = HPMC_OK;
         for (size_t q = 0; q < order.size(); ++q) {
             unpack_counters(&hc[q * kCounterStride], &out[order[q]]);
+            out[order[q]].sweep_ms = all;  // the whole batch's sweeps (phase launches not timed apart)
             const int f = static_cast<int>(hc[q * kCounterStride + kNumCounters]);
             if (f) {
                 hpmc_sim* x = sims[order[q]];

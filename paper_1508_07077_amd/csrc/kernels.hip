@@ -1310,16 +1310,13 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const WorkG& 
                 Vec3 xn;
                 {
                     uint32_t tw0 = rdlane_u(w.w0, 1), tw1 = rdlane_u(w.w1, 1), tw2 = rdlane_u(w.w2, 1);
-                    double v;
-                    v = pj.x + P.d_trans * sym01(tw0);
-                    if (v >= P.L) v -= P.L; else if (v < 0.0) v += P.L;
-                    xn.x = v;
-                    v = pj.y + P.d_trans * sym01(tw1);
-                    if (v >= P.L) v -= P.L; else if (v < 0.0) v += P.L;
-                    xn.y = v;
-                    v = pj.z + P.d_trans * sym01(tw2);
-                    if (v >= P.L) v -= P.L; else if (v < 0.0) v += P.L;
-                    xn.z = v;
+                    auto wrapL = [&](double v) {
+                        const double a = v - P.L, b = v + P.L;
+                        return v >= P.L ? a : (v < 0.0 ? b : v);
+                    };
+                    xn.x = wrapL(pj.x + P.d_trans * sym01(tw0));
+                    xn.y = wrapL(pj.y + P.d_trans * sym01(tw1));
+                    xn.z = wrapL(pj.z + P.d_trans * sym01(tw2));
                 }
                 TrialOut o{0, 0, 0, 0, 0, 0, 0, false};
                 if (cell_of(P, xn.x, xn.y, xn.z, g0, g1, g2) != C) {
