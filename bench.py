@@ -557,6 +557,14 @@ def bench_c4(args):
                      tot["trials"] / args.steps, dev_ms / 1e3 / args.steps,
                      "phase_oriented_kernel<discoid> (two launch groups per phase; the time is the whole batched "
                      "sweep on the device, cell lists included)", per="sweep")
+    # the same batch, untimed calls of several sweeps: one captured sweep replayed
+    torch.cuda.synchronize()
+    tg = time.perf_counter()
+    b.sweep(args.steps, counters=False)
+    torch.cuda.synchronize()
+    dtg = time.perf_counter() - tg
+    graph = {"moves_per_s": args.steps * sum(x.n for x in sims) / dtg, "ms_per_sweep": dtg * 1e3 / args.steps,
+             "note": "one call of `steps` sweeps without counters: a captured batched sweep replayed"}
     alone = None
     # the same replicas swept one at a time (each handle's own launches), for comparison
     for x in (sims if args.alone else []):
@@ -575,7 +583,8 @@ def bench_c4(args):
                  f"256 swept-disk replicas, N={sum(s.n for s in sps)} in total (128..8192 each), "
                  "phi_c U[0.05,0.45], eta_r U[0,0.5], q=0.2, one launch per kernel for all replicas",
                  {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                  "replicas": len(sps), "launch_tuning": tuning, "one_at_a_time": alone, "roofline": roof})
+                  "replicas": len(sps), "launch_tuning": tuning, "graph_replay": graph, "one_at_a_time": alone,
+                  "roofline": roof})
 
 
 def bench_c5(args):

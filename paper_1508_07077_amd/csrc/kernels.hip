@@ -1243,6 +1243,37 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const WorkG& 
         }
     }
     unsigned long long todo = __ballot(nck > 0);
+
+    // Trial slots of the chunk: cell k's n_select * n_c trials take slots
+    // offk .. offk + ntrk - 1, in cell order.  A trial's own draws (selection,
+    // translation, acceptance and its Poisson chunks: B Philox blocks) depend
+    // on the random streams alone, not on the state, so those of T = 64 / B
+    // trials are drawn at once, one block per lane (and the Poisson chunks
+    // resolved there), and read across lanes when each trial runs.
+    const int ntrk = P.n_select * nck;
+    int nslots;
+    const int offk = wave_excl_scan(ntrk, nslots);
+    const int B = 3 + P.n_chunks < 64 ? 3 + P.n_chunks : 64;
+    const int T = 64 / B;
+    int sb = -64;  // first slot of the batch in the lanes (none yet)
+    Words wb{0u, 0u, 0u, 0u};
+    int jlb = 0, kcb = 0;
+    auto draw_batch = [&](int s0) {
+        const int tl = lane / B, q = lane - tl * B;
+        const int sl = s0 + tl;
+        // the cell of slot sl (slots of a cell are contiguous, cells in order)
+        int k = 0;
+        for (int kk = 1; kk < P.chunk; ++kk)
+            if (static_cast<int>(rdlane_u(static_cast<uint32_t>(offk), kk)) <= sl) k = kk;
+        const int o = __shfl(offk, k, 64), nk = __shfl(nck, k, 64), Cs = __shfl(Ck, k, 64);
+        const bool valid = tl < T && sl < nslots;
+        const uint32_t purpose = q == 0 ? kSelect : (q == 1 ? kTrans : (q == 2 ? kAccept : kPoisson));
+        const uint32_t index = q >= 3 ? static_cast<uint32_t>(q - 3) : 0u;
+        wb = draw(P, static_cast<uint32_t>(Cs), static_cast<uint32_t>(sl - o), purpose, index);
+        jlb = static_cast<int>(pick(wb.w0, static_cast<uint32_t>(nk > 0 ? nk : 1)));
+        kcb = 0;
+        if (valid && P.has_dep && q >= 3 && q - 3 < P.n_chunks) kcb = poisson_guided(sF, sG, u52(wb.w0, wb.w1));
+    };
     // ranges of the stencil of chunk cell k (k < 0: none)
     auto ranges_of = [&](int k, int& es, int& ec) {
         const NbOff nb = nb_offset(P.n);
@@ -1279,6 +1310,7 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const WorkG& 
         const int start = static_cast<int>(rdlane_u(static_cast<uint32_t>(startk), kc));
         const int nc = static_cast<int>(rdlane_u(static_cast<uint32_t>(nck), kc));
         const int nst = nst_cur;
+        const int slot0 = static_cast<int>(rdlane_u(static_cast<uint32_t>(offk), kc));
         // start staging the next cell while this one runs
         int kn2 = next_cell(rem);
         int nst_next = 0;
@@ -1291,25 +1323,19 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const WorkG& 
         } else {
             const int ntr = P.n_select * nc;
             for (int t = 0; t < ntr; ++t) {
-                // --- per-trial draws packed across lanes -----------------------
-                uint32_t purpose = 0, index = 0;
-                if (lane == 0) {
-                    purpose = kSelect;
-                } else if (lane == 1) {
-                    purpose = kTrans;
-                } else if (lane == 2) {
-                    purpose = kAccept;
-                } else {
-                    purpose = kPoisson;
-                    index = static_cast<uint32_t>(lane - 3);
+                // --- this trial's draws, from the batch in the lanes -------------
+                const int slot = slot0 + t;
+                if (slot >= sb + T) {
+                    sb = slot;
+                    draw_batch(sb);
                 }
-                Words w = draw(P, static_cast<uint32_t>(C), static_cast<uint32_t>(t), purpose, index);
-                const int jl = static_cast<int>(pick(rdlane_u(w.w0, 0), static_cast<uint32_t>(nc)));
+                const int base = (slot - sb) * B;
+                const int jl = static_cast<int>(rdlane_u(static_cast<uint32_t>(jlb), base));
                 // own members are entries 0 .. nc-1: staged, or (past the stage) in HBM
                 const double4 pj = jl < kStage ? stage_rec(S0, jl) : rd4(W.rpos, start + jl);
                 Vec3 xn;
                 {
-                    uint32_t tw0 = rdlane_u(w.w0, 1), tw1 = rdlane_u(w.w1, 1), tw2 = rdlane_u(w.w2, 1);
+                    uint32_t tw0 = rdlane_u(wb.w0, base + 1), tw1 = rdlane_u(wb.w1, base + 1), tw2 = rdlane_u(wb.w2, base + 1);
                     auto wrapL = [&](double v) {
                         const double a = v - P.L, b = v + P.L;
                         return v >= P.L ? a : (v < 0.0 ? b : v);
@@ -1342,21 +1368,21 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const WorkG& 
                     if (__ballot(hit) != 0ull) {
                         o.reason = 2;
                     } else if (P.has_dep) {
-                        int kcnt = 0;
-                        if (lane >= 3 && lane - 3 < P.n_chunks) kcnt = poisson_guided(sF, sG, u52(w.w0, w.w1));
-                        for (int base = 61; base < P.n_chunks; base += 64) {
-                            int ci = base + lane;
+                        // chunk counts sit in lanes base + 3 .. base + 2 + n_chunks; chunks past
+                        // lane 63 (more than 61 of them: then one trial per batch) are drawn here
+                        int kx = (lane >= base + 3 && lane < base + 3 + P.n_chunks) ? kcb : 0;
+                        for (int cbase = 61; cbase < P.n_chunks; cbase += 64) {
+                            int ci = cbase + lane;
                             if (ci < P.n_chunks) {
                                 Words pw = draw(P, static_cast<uint32_t>(C), static_cast<uint32_t>(t), kPoisson,
                                                 static_cast<uint32_t>(ci));
-                                kcnt += poisson_guided(sF, sG, u52(pw.w0, pw.w1));
+                                kx += poisson_guided(sF, sG, u52(pw.w0, pw.w1));
                             }
                         }
-                        // chunk counts sit in lanes 3 .. 3 + n_chunks - 1 (more chunks: in every lane)
-                        const uint32_t Np = static_cast<uint32_t>(P.n_chunks <= 8 ? lanes_sum(kcnt, 3, P.n_chunks)
-                                                                                  : wave_sum(kcnt));
+                        const uint32_t Np = static_cast<uint32_t>(P.n_chunks <= 8 ? lanes_sum(kcb, base + 3, P.n_chunks)
+                                                                                  : wave_sum(kx));
                         o.n_dep = Np;
-                        const double au = u52(rdlane_u(w.w0, 2), rdlane_u(w.w1, 2));
+                        const double au = u52(rdlane_u(wb.w0, base + 2), rdlane_u(wb.w1, base + 2));
                         const Vec3 Dold = v3(mi(P, pj.x - xn.x), mi(P, pj.y - xn.y), mi(P, pj.z - xn.z));
                         double ratio = 1.0;
                         bool done = false;
