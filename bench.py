@@ -107,6 +107,8 @@ def parse():
                     help="c5: requests of the trace served all at once, batched and one at a time")
     ap.add_argument("--eta", default="0.1,0.2,0.3,0.4",
                     help="c2: comma-separated reservoir packing fractions eta_r to run")
+    ap.add_argument("--no-batch", dest="batch", action="store_false",
+                    help="c2: skip the leg that sweeps the state points together (value is then one at a time)")
     ap.add_argument("--no-fp32", dest="fp32", action="store_false",
                     help="c2, c3: skip the FP32-guarded companion run")
     ap.add_argument("--no-companion", dest="companion", action="store_false",
@@ -464,6 +466,7 @@ def bench_c2(args):
     moves = checks = secs = 0.0
     lat = []
     fp32 = {}
+    kept = []
     profiled = kernel_digest() == PROFILED_KERNEL_DIGEST
     for eta in [float(x) for x in args.eta.split(",")]:
         sp = wl.c2_hemispheres(eta)
@@ -492,6 +495,7 @@ def bench_c2(args):
         moves += tot["trials"]
         checks += tot["depletants_resolved"]
         secs += dt
+        kept.append(sim)
         if not args.fp32:
             continue
         # the same state point with FP32 depletant predicates and the FP64 guard band
@@ -507,12 +511,49 @@ def bench_c2(args):
         fp32[str(eta)] = {"moves_per_s": t3["trials"] / dt3, "fp64_fallbacks": t3["fp64_fallbacks"],
                           "fp64_fallbacks_per_depletant": t3["fp64_fallbacks"] / max(t3["depletants_drawn"], 1)}
         s32.close()
-    d = _line(moves / secs, {"depletants_resolved": checks, "accepts": 1, "trials": 1}, secs, 4 * args.steps,
-              3, "hemispheres N=16384 phi_c=0.20 q=0.15 eta_r in {0.1,0.2,0.3,0.4}, p_rot=0.5, FP64",
-              {"per_eta_r": per, "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+    if not args.batch:
+        for x in kept:
+            x.close()
+        d = _line(moves / secs, {"depletants_resolved": checks, "accepts": 1, "trials": 1}, secs, len(per) * args.steps,
+                  3, f"hemispheres N=16384 phi_c=0.20 q=0.15 eta_r in {{{args.eta}}}, p_rot=0.5, FP64, one at a time",
+                  {"per_eta_r": per, "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                   "fp32_guarded_per_eta_r": fp32,
+                   "roofline": roofs.get("0.4", roofs[max(roofs)]) if roofs else None})
+        d.pop("acceptance")
+        return d
+    # the state points swept together: one batched launch per phase for all of
+    # them (independent replicas, each with its own random streams), which gives
+    # the device len(eta) times the independent cells of one state point
+    b = hp.Batch(kept)
+    for _ in range(3):
+        b.sweep(1, counters=True)
+    torch.cuda.synchronize()
+    btot = None
+    dev_ms = 0.0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        cs = b.sweep(1, counters=True)
+        dev_ms += cs[0]["sweep_ms"]
+        c = {k: sum(x[k] for x in cs) for k in cs[0] if k != "sweep_ms"}
+        btot = c if btot is None else {k: btot[k] + c[k] for k in btot}
+    bdt = time.perf_counter() - t0
+    broof = _roofline("hemisphere", profiled, btot["depletants_resolved"] / args.steps, btot["trials"] / args.steps,
+                      dev_ms / 1e3 / args.steps,
+                      "phase_oriented_kernel<hemisphere> (one launch per phase for all state points; the time is "
+                      "the whole batched sweep on the device, cell lists included)", per="sweep")
+    for x in kept:
+        x.close()
+    one_at_a_time = {"moves_per_s": moves / secs, "depletant_checks_per_s": checks / secs,
+                     "note": "each state point swept alone, one after the other"}
+    d = _line(btot["trials"] / bdt, btot, bdt, args.steps, 3,
+              f"hemispheres N=16384 phi_c=0.20 q=0.15 eta_r in {{{args.eta}}}, p_rot=0.5, FP64, "
+              "the state points swept together",
+              {"per_eta_r": per, "one_at_a_time": one_at_a_time, "batched_ms_per_sweep": bdt * 1e3 / args.steps,
+               "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                "fp32_guarded_per_eta_r": fp32,
-               # the state point with the most depletant work (the profiled one when it ran)
-               "roofline": roofs.get("0.4", roofs[max(roofs)]) if roofs else None})
+               "roofline": broof,
+               # one state point alone, per launch (the one with the most depletant work)
+               "roofline_one_state_point": roofs.get("0.4", roofs[max(roofs)]) if roofs else None})
     d.pop("acceptance")
     return d
 
