@@ -59,19 +59,19 @@ def shell_ops_per_check(R0: float, r_i: float) -> float:
 # busy with active lanes (rocprofv3 VALUBusy x VALUUtilization).  The HBM bytes
 # per launch are FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the factors a plain
 # 256 MiB device copy reads off the same counters).
-PROFILED_KERNEL_DIGEST = "36915d0909f6f47f"
+PROFILED_KERNEL_DIGEST = "9f6368cd8b3d5fe6"
 PROFILE = {
     # 1,048,576 spheres, ball region, 212.05 resolved checks per move
-    "sphere": {"a_dep": 172.09, "b_move": 15854.4, "valu_instr_per_move": 1207.4, "valu_busy": 66.86,
-               "valu_utilization": 67.74, "traffic_bytes_per_launch": 67611067},
+    "sphere": {"a_dep": 175.71, "b_move": 13732.1, "valu_instr_per_move": 1195.6, "valu_busy": 66.70,
+               "valu_utilization": 66.64, "traffic_bytes_per_launch": 67613141},
     # 16,384 hemispheres at eta_r 0.4, 72.31 resolved checks per move
-    "hemisphere": {"a_dep": 393.34, "b_move": 32966.0, "valu_instr_per_move": 2142.3, "valu_busy": 12.35,
-                   "valu_utilization": 44.79, "traffic_bytes_per_launch": 4455252},
+    "hemisphere": {"a_dep": 393.75, "b_move": 32422.4, "valu_instr_per_move": 2074.9, "valu_busy": 12.05,
+                   "valu_utilization": 45.86, "traffic_bytes_per_launch": 4438863},
     # 256 swept-disk replicas, both launch groups of a phase, 56.50 resolved checks per move
-    "discoid": {"a_dep": 483.28, "b_move": 29808.9, "valu_instr_per_move": 2428.0,
-                "valu_busy": {"replicas of two cells per axis": 0.85, "the others": 43.87},
-                "valu_utilization": {"replicas of two cells per axis": 34.11, "the others": 36.80},
-                "traffic_bytes_per_phase": 93871679},
+    "discoid": {"a_dep": 479.65, "b_move": 29293.9, "valu_instr_per_move": 2323.9,
+                "valu_busy": {"replicas of two cells per axis": 0.83, "the others": 42.71},
+                "valu_utilization": {"replicas of two cells per axis": 35.23, "the others": 37.96},
+                "traffic_bytes_per_phase": 93861871},
 }
 
 
