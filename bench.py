@@ -398,6 +398,16 @@ def _make(hp, sp, melt=20):
     return _finish(sim, sp)
 
 
+def _group_shapes(shapes):
+    """the launch shapes hpmc_autotune_batch chose, one entry per launch group"""
+    groups = {}
+    for t in shapes:
+        key = (t["cells_per_wave"], t["waves_per_block"], t["max_waves"], t["best_ms"], t["default_ms"])
+        g = groups.setdefault(key, dict(t, replicas=0))
+        g["replicas"] += 1
+    return list(groups.values())
+
+
 def _line(metric_value, tot, dt, steps, warmup, workload, extra):
     d = {
         "metric": "colloid trial moves/s + depletant overlap checks/s (1 GPU); p50/p99 latency",
@@ -525,6 +535,7 @@ def bench_c2(args):
     # them (independent replicas, each with its own random streams), which gives
     # the device len(eta) times the independent cells of one state point
     b = hp.Batch(kept)
+    btuning = _group_shapes(b.autotune(sweeps=2)) if args.autotune else None
     for _ in range(3):
         b.sweep(1, counters=True)
     torch.cuda.synchronize()
@@ -549,6 +560,7 @@ def bench_c2(args):
               f"hemispheres N=16384 phi_c=0.20 q=0.15 eta_r in {{{args.eta}}}, p_rot=0.5, FP64, "
               "the state points swept together",
               {"per_eta_r": per, "one_at_a_time": one_at_a_time, "batched_ms_per_sweep": bdt * 1e3 / args.steps,
+               "batch_launch_tuning": btuning,
                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                "fp32_guarded_per_eta_r": fp32,
                "roofline": broof,
@@ -571,14 +583,9 @@ def bench_c4(args):
     sims = [_prepare(hp, sp) for sp in sps]
     hp.Batch(sims).sweep(20, counters=False)  # the untimed melt, all replicas together
     sims = [_finish(x, sp) for x, sp in zip(sims, sps)]
-    tuning = None
-    if args.autotune:
-        # the batch launches with the shape of its first handle: tune the largest replica
-        big = max(sims, key=lambda x: x.n)
-        tuning = big.autotune(sweeps=2)
-        for x in sims:
-            x.set_tuning(tuning["cells_per_wave"], tuning["waves_per_block"], tuning["max_waves"])
     b = hp.Batch(sims)
+    # per launch group: the candidate shapes timed with the group's members swept together
+    tuning = _group_shapes(b.autotune(sweeps=2)) if args.autotune else None
     for _ in range(3):
         b.sweep(1, counters=True)
     torch.cuda.synchronize()

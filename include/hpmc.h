@@ -245,7 +245,8 @@ typedef struct hpmc_tuning {
 } hpmc_tuning;
 
 /* Set the launch shape explicitly (the last three fields are ignored).
- * Batched sweeps use the shape of the first handle of each group.
+ * Batched sweeps use the shape of the most crowded handle of each group
+ * (hpmc_autotune_batch gives a group's handles one shape).
  * Errors: EINVAL (a field out of range). */
 int hpmc_set_tuning(hpmc_sim* sim, const hpmc_tuning* tuning);
 
@@ -278,6 +279,27 @@ int hpmc_batch_workspace_bytes(int n_sims, size_t* bytes);
  * ESTATE, ENOMEM, EHIP, ECAPACITY (as for hpmc_sweep, per replica). */
 int hpmc_sweep_batch(hpmc_sim* const* sims, int n_sims, void* batch_ws, size_t bytes, int n_sweeps,
                      hpmc_counters* out);
+
+/* Autotuner of a batch (run-time tuning of launch shapes, App. A, applied to
+ * the batched sweeps of Sec. III.E): for each launch group of
+ * hpmc_sweep_batch (replicas of one shape kind, precision and insertion
+ * region; small sphere boxes, which sweep in one workgroup each, and oriented
+ * boxes of two cells per axis apart), time the candidate shapes of
+ * hpmc_autotune with that group's members swept together, and give every
+ * member of the group the fastest.  The sweeps run on copies of the states:
+ * states, sweep indices and traces are as before the call, and trajectories
+ * do not depend on the shape.  Same conditions as hpmc_sweep_batch (ready
+ * handles, tracing off, the stream of sims[0], batch_ws of
+ * hpmc_batch_workspace_bytes(n_sims)); each handle at most once.
+ * scratch: device memory for every member's state, members in order, each
+ * N*24 bytes (+ N*32 for oriented shapes) rounded up to 256 bytes.
+ * sweeps: 1..64 timed per candidate (after one untimed).  out: NULL or n_sims
+ * records (best_ms / default_ms: device ms per batched sweep of the member's
+ * group; candidates is 0 for a small sphere box).  Synchronous.
+ * Errors: EINVAL, ESTATE, ENOMEM, EHIP, ECAPACITY; on error every handle keeps
+ * its state and its previous launch shape. */
+int hpmc_autotune_batch(hpmc_sim* const* sims, int n_sims, void* batch_ws, size_t ws_bytes, void* scratch,
+                        size_t scratch_bytes, int sweeps, hpmc_tuning* out);
 
 /* Observables of the current state (host out, synchronous):
  *   HPMC_OBS_GR: out[0..n_bins) = g(r) of reference-point distances on

@@ -52,6 +52,7 @@ EXPORTS = (
     "hpmc_sweep_batch",
     "hpmc_set_tuning",
     "hpmc_autotune",
+    "hpmc_autotune_batch",
 )
 
 COUNTERS = (
@@ -146,6 +147,8 @@ def lib():
         L.hpmc_sweep_batch.argtypes = [ctypes.POINTER(vp), cint, vp, ctypes.c_size_t, cint, ctypes.POINTER(_Counters)]
         L.hpmc_set_tuning.argtypes = [vp, ctypes.POINTER(_Tuning)]
         L.hpmc_autotune.argtypes = [vp, vp, ctypes.c_size_t, cint, ctypes.POINTER(_Tuning)]
+        L.hpmc_autotune_batch.argtypes = [ctypes.POINTER(vp), cint, vp, ctypes.c_size_t, vp, ctypes.c_size_t, cint,
+                                          ctypes.POINTER(_Tuning)]
         for name in EXPORTS:
             if name not in ("hpmc_destroy", "hpmc_last_error"):
                 getattr(L, name).restype = cint
@@ -348,3 +351,20 @@ class Batch:
         for d, c in zip(res, out):
             d["sweep_ms"] = float(c.sweep_ms)
         return res
+
+    def autotune(self, sweeps: int = 2) -> list:
+        """Per launch group, time the candidate launch shapes with the group's
+        members swept together (on copies of their states) and give them the
+        fastest; returns each member's shape (hpmc_autotune_batch)."""
+        n = len(self.sims)
+        need = sum((s.n * 24 + (s.n * 32 if s.kind != SPHERE else 0) + 255) // 256 * 256 for s in self.sims)
+        scratch = self.torch.empty(max(need, 1), dtype=self.torch.uint8, device=self.workspace.device)
+        out = (_Tuning * n)()
+        rc = lib().hpmc_autotune_batch(self._handles, n, ctypes.c_void_p(self.workspace.data_ptr()),
+                                       self.workspace.numel(), ctypes.c_void_p(scratch.data_ptr()), need,
+                                       int(sweeps), out)
+        del scratch
+        if rc != 0:
+            msg = lib().hpmc_last_error(self.sims[0]._h) if n else b""
+            raise HpmcError(rc, f"autotune_batch: {msg.decode() if msg else ''}")
+        return [{f: getattr(t, f) for f, _ in _Tuning._fields_} for t in out]

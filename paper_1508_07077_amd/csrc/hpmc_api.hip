@@ -404,6 +404,37 @@ Group make_group(const Desc* d, const hpmc_sim* const* sims, int n)
     return g;
 }
 
+// Launch group of a replica in a batched sweep: replicas of one shape kind,
+// precision and insertion region share the phase launches, except that small
+// sphere boxes (one workgroup sweeps each) and oriented boxes with a large
+// geometry cache (few active cells, long serial chains; their LDS would lower
+// everyone's occupancy) form groups of their own.
+int batch_class(const hpmc_sim* s, const Params& P)
+{
+    const int small = (s->S.kind == HPMC_SPHERE && P.active_cells <= kSmallMaxActive && P.N <= kSmallMaxN &&
+                       kTableLds + static_cast<size_t>(kSmallWaves) * P.wave_lds + kSmallStaticLds <= lds_limit())
+                          ? 1
+                          : 0;
+    const int dense = s->S.oriented && P.geo_cap > 64 ? 1 : 0;
+    return 16 * s->S.kind + 8 * dense + 4 * small + 2 * s->precision + s->region;
+}
+constexpr int kBatchClasses = 48;
+int class_is_small(int cl) { return (cl >> 2) & 1; }
+
+// launch shapes the autotuners time; the first is the default
+std::vector<hpmc_tuning> tuning_candidates(bool oriented)
+{
+    std::vector<hpmc_tuning> cand;
+    if (!oriented) {
+        for (int c : {16, 4, 8, 10, 12, 32, 64})
+            for (int w : {4, 2, 1}) cand.push_back(hpmc_tuning{c, w, 0, 0, 0.0, 0.0});
+    } else {
+        for (int m : {kMaxWaves, 1024, 2048, 4096, 16384, 32768})
+            for (int w : {4, 2, 1}) cand.push_back(hpmc_tuning{0, w, m, 0, 0.0, 0.0});
+    }
+    return cand;
+}
+
 Desc make_desc(const hpmc_sim* s, int wpb, int chunk)
 {
     Desc d{};
@@ -1017,15 +1048,7 @@ int hpmc_autotune(hpmc_sim* s, void* scratch, size_t bytes, int sweeps, hpmc_tun
     const size_t N = static_cast<size_t>(s->N);
     const size_t need = N * 3 * sizeof(double) + (s->S.oriented ? N * 4 * sizeof(double) : 0);
     if (bytes < need) return fail(s, HPMC_ENOMEM, "autotune scratch smaller than the state");
-    // candidates
-    std::vector<hpmc_tuning> cand;
-    if (!s->S.oriented) {
-        for (int c : {16, 4, 8, 10, 12, 32, 64})
-            for (int w : {4, 2, 1}) cand.push_back(hpmc_tuning{c, w, 0, 0, 0.0, 0.0});
-    } else {
-        for (int m : {kMaxWaves, 1024, 2048, 4096, 16384, 32768})
-            for (int w : {4, 2, 1}) cand.push_back(hpmc_tuning{0, w, m, 0, 0.0, 0.0});
-    }
+    const std::vector<hpmc_tuning> cand = tuning_candidates(s->S.oriented != 0);
     // run on a copy of the state; restore everything afterwards
     double* pos0 = s->pos;
     double* quat0 = s->quat;
@@ -1176,22 +1199,8 @@ int hpmc_sweep_batch(hpmc_sim* const* sims, int n_sims, void* batch_ws, size_t b
     unsigned long long* d_gather = reinterpret_cast<unsigned long long*>(base + bl.gather);
     std::vector<Params> par(static_cast<size_t>(n_sims));
     for (int i = 0; i < n_sims; ++i) par[static_cast<size_t>(i)] = make_params(sims[i]);
-    // small sphere boxes form their own groups (one workgroup sweeps each);
-    // oriented boxes with a large geometry cache (dense: few active cells, long
-    // serial chains) too, so that their LDS does not lower everyone's occupancy
-    auto small_ok = [&](int i) {
-        const Params& Pi = par[static_cast<size_t>(i)];
-        if (sims[i]->S.kind != HPMC_SPHERE) return 0;
-        return (Pi.active_cells <= kSmallMaxActive && Pi.N <= kSmallMaxN &&
-                kTableLds + static_cast<size_t>(kSmallWaves) * Pi.wave_lds + kSmallStaticLds <= lds_limit())
-                   ? 1
-                   : 0;
-    };
-    auto dense = [&](int i) { return sims[i]->S.oriented && par[static_cast<size_t>(i)].geo_cap > 64 ? 1 : 0; };
     std::vector<int> cl(static_cast<size_t>(n_sims));
-    for (int i = 0; i < n_sims; ++i)
-        cl[static_cast<size_t>(i)] =
-            16 * sims[i]->S.kind + 8 * dense(i) + 4 * small_ok(i) + 2 * sims[i]->precision + sims[i]->region;
+    for (int i = 0; i < n_sims; ++i) cl[static_cast<size_t>(i)] = batch_class(sims[i], par[static_cast<size_t>(i)]);
     auto cls = [&](int i) { return cl[static_cast<size_t>(i)]; };
     // within a group, the most crowded cells first: their blocks are dispatched
     // first, since their serial chains of trials set the length of a phase
@@ -1200,7 +1209,7 @@ int hpmc_sweep_batch(hpmc_sim* const* sims, int n_sims, void* batch_ws, size_t b
         return static_cast<double>(Pi.N) / static_cast<double>(Pi.ncells);
     };
     std::vector<int> order;
-    for (int k = 0; k < 48; ++k) {
+    for (int k = 0; k < kBatchClasses; ++k) {
         const size_t first = order.size();
         for (int i = 0; i < n_sims; ++i)
             if (cls(i) == k) order.push_back(i);
@@ -1292,6 +1301,128 @@ int hpmc_sweep_batch(hpmc_sim* const* sims, int n_sims, void* batch_ws, size_t b
             }
         }
         return r;
+    }
+    return HPMC_OK;
+}
+
+int hpmc_autotune_batch(hpmc_sim* const* sims, int n_sims, void* batch_ws, size_t ws_bytes, void* scratch,
+                        size_t scratch_bytes, int sweeps, hpmc_tuning* out)
+{
+    if (!sims || n_sims < 1) return HPMC_EINVAL;
+    for (int i = 0; i < n_sims; ++i)
+        if (!sims[i]) return HPMC_EINVAL;
+    hpmc_sim* s0 = sims[0];
+    if (!scratch || sweeps < 1 || sweeps > 64) return fail(s0, HPMC_EINVAL, "autotune needs scratch and 1..64 sweeps");
+    std::vector<const hpmc_sim*> sorted(sims, sims + n_sims);
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+        return fail(s0, HPMC_EINVAL, "a handle appears twice in the batch");
+    std::vector<int> cl(static_cast<size_t>(n_sims));
+    std::vector<size_t> off(static_cast<size_t>(n_sims));
+    size_t need = 0;
+    for (int i = 0; i < n_sims; ++i) {
+        hpmc_sim* x = sims[i];
+        int r = check_ready(x, true);
+        if (r != HPMC_OK) return r;
+        if (x->trace) return fail(x, HPMC_EINVAL, "tracing is per handle; disable it for batched sweeps");
+        cl[static_cast<size_t>(i)] = batch_class(x, make_params(x));
+        off[static_cast<size_t>(i)] = need;
+        const size_t N = static_cast<size_t>(x->N);
+        need += (N * 3 * sizeof(double) + (x->S.oriented ? N * 4 * sizeof(double) : 0) + 255) / 256 * 256;
+    }
+    if (scratch_bytes < need) return fail(s0, HPMC_ENOMEM, "autotune scratch smaller than the states of the batch");
+    // every member sweeps a copy of its state; pointers, sweep index and
+    // launch shape are restored afterwards
+    struct Saved {
+        double* pos;
+        double* quat;
+        uint64_t sweep;
+        int chunk, wpb, waves;
+    };
+    std::vector<Saved> sv(static_cast<size_t>(n_sims));
+    hipStream_t st = s0->stream;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < n_sims && e == hipSuccess; ++i) {
+        hpmc_sim* x = sims[i];
+        const size_t N = static_cast<size_t>(x->N);
+        sv[static_cast<size_t>(i)] = Saved{x->pos, x->quat, x->sweep, x->tune_chunk, x->tune_wpb, x->tune_waves};
+        double* cp = reinterpret_cast<double*>(static_cast<unsigned char*>(scratch) + off[static_cast<size_t>(i)]);
+        double* cq = x->S.oriented ? cp + 3 * N : nullptr;
+        e = hipMemcpyAsync(cp, x->pos, N * 3 * sizeof(double), hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess && cq) e = hipMemcpyAsync(cq, x->quat, N * 4 * sizeof(double), hipMemcpyDeviceToDevice, st);
+        x->pos = cp;
+        x->quat = cq;
+        x->W.pos = cp;
+        x->W.quat = cq;
+        x->desc_dirty = 1;
+    }
+    int r = e == hipSuccess ? HPMC_OK : hip_fail(s0, e, "autotune copy");
+    std::vector<hpmc_tuning> chosen(static_cast<size_t>(n_sims));
+    for (int i = 0; i < n_sims; ++i)
+        chosen[static_cast<size_t>(i)] = hpmc_tuning{sims[i]->tune_chunk, sims[i]->tune_wpb, sims[i]->tune_waves, 0, 0.0, 0.0};
+    // each launch group alone: the candidate shapes on all its members at once
+    for (int k = 0; k < kBatchClasses && r == HPMC_OK; ++k) {
+        std::vector<hpmc_sim*> mem;
+        for (int i = 0; i < n_sims; ++i)
+            if (cl[static_cast<size_t>(i)] == k) mem.push_back(sims[i]);
+        if (mem.empty() || class_is_small(k)) continue;  // one workgroup per small replica: no shape to tune
+        const std::vector<hpmc_tuning> cand = tuning_candidates(mem[0]->S.oriented != 0);
+        std::vector<hpmc_counters> cnt(mem.size());
+        int best = -1;
+        double best_ms = 0.0, default_ms = 0.0;
+        for (size_t c = 0; c < cand.size() && r == HPMC_OK; ++c) {
+            for (hpmc_sim* x : mem) {
+                x->tune_chunk = cand[c].cells_per_wave;
+                x->tune_wpb = cand[c].waves_per_block;
+                x->tune_waves = cand[c].max_waves;
+                x->desc_dirty = 1;
+            }
+            const int nm = static_cast<int>(mem.size());
+            r = hpmc_sweep_batch(mem.data(), nm, batch_ws, ws_bytes, 1, nullptr);
+            if (r == HPMC_OK) r = hpmc_sweep_batch(mem.data(), nm, batch_ws, ws_bytes, sweeps, cnt.data());
+            if (r != HPMC_OK) break;
+            const double ms = cnt[0].sweep_ms / sweeps;
+            if (c == 0) default_ms = ms;
+            if (best < 0 || ms < best_ms) {
+                best = static_cast<int>(c);
+                best_ms = ms;
+            }
+        }
+        if (r != HPMC_OK) break;
+        for (int i = 0; i < n_sims; ++i)
+            if (cl[static_cast<size_t>(i)] == k) {
+                chosen[static_cast<size_t>(i)] = cand[static_cast<size_t>(best)];
+                chosen[static_cast<size_t>(i)].candidates = static_cast<int32_t>(cand.size());
+                chosen[static_cast<size_t>(i)].best_ms = best_ms;
+                chosen[static_cast<size_t>(i)].default_ms = default_ms;
+            }
+    }
+    // restore every member (also after an error), then hand out the shapes
+    for (int i = 0; i < n_sims; ++i) {
+        hpmc_sim* x = sims[i];
+        const Saved& v = sv[static_cast<size_t>(i)];
+        if (!v.pos) continue;  // not reached by the copy loop
+        x->pos = v.pos;
+        x->quat = v.quat;
+        x->W.pos = v.pos;
+        x->W.quat = v.quat;
+        x->sweep = v.sweep;
+        x->trace_valid = 0;
+        x->tune_chunk = v.chunk;
+        x->tune_wpb = v.wpb;
+        x->tune_waves = v.waves;
+        x->desc_dirty = 1;
+        int r2 = set_sweep_dev(x);
+        if (r == HPMC_OK && r2 != HPMC_OK) r = r2;
+    }
+    e = hipStreamSynchronize(st);
+    if (r == HPMC_OK && e != hipSuccess) r = hip_fail(s0, e, "autotune");
+    if (r != HPMC_OK) return r;
+    for (int i = 0; i < n_sims; ++i) {
+        sims[i]->tune_chunk = chosen[static_cast<size_t>(i)].cells_per_wave;
+        sims[i]->tune_wpb = chosen[static_cast<size_t>(i)].waves_per_block;
+        sims[i]->tune_waves = chosen[static_cast<size_t>(i)].max_waves;
+        if (out) out[i] = chosen[static_cast<size_t>(i)];
     }
     return HPMC_OK;
 }
