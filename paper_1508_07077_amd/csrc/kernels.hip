@@ -796,25 +796,31 @@ __device__ __forceinline__ void phase_body(const Params& P, const WorkG& W, int 
             wave_sync();
         }
 
+        // A trial's own draws (selection, translation, acceptance and its
+        // Poisson chunks: B Philox blocks) depend on the random streams alone,
+        // not on the state, so those of T = 64 / B consecutive trials of the
+        // cell are drawn at once, one block per lane (the Poisson chunks
+        // resolved there), and read across lanes when each trial runs.
+        // Rotation candidates are drawn by the trials that rotate.
         const int ntr = P.n_select * c.nc;
+        const int B = 3 + P.n_chunks < 64 ? 3 + P.n_chunks : 64;
+        const int T = 64 / B;
+        int tb = -64;  // first trial of the batch in the lanes (none yet)
+        Words wb{0u, 0u, 0u, 0u};
+        int kcb = 0;
         for (int t = 0; t < ntr; ++t) {
-            // --- per-trial draws packed across lanes ---------------------------
-            uint32_t purpose = 0, index = 0;
-            if (lane == 0) {
-                purpose = kSelect;
-            } else if (lane == 1) {
-                purpose = kTrans;
-            } else if (lane == 2) {
-                purpose = kAccept;
-            } else if (lane < 32) {
-                purpose = kPoisson;
-                index = static_cast<uint32_t>(lane - 3);
-            } else {
-                purpose = kRot;
-                index = static_cast<uint32_t>(lane - 32);
+            if (t >= tb + T) {
+                tb = t;
+                const int tl = lane / B, q = lane - tl * B;
+                const bool valid = tl < T && tb + tl < ntr;
+                const uint32_t purpose = q == 0 ? kSelect : (q == 1 ? kTrans : (q == 2 ? kAccept : kPoisson));
+                const uint32_t index = q >= 3 ? static_cast<uint32_t>(q - 3) : 0u;
+                wb = draw(P, static_cast<uint32_t>(C), static_cast<uint32_t>(tb + tl), purpose, index);
+                kcb = 0;
+                if (valid && P.has_dep && q >= 3 && q - 3 < P.n_chunks) kcb = poisson_guided(sF, sG, u52(wb.w0, wb.w1));
             }
-            Words w = draw(P, static_cast<uint32_t>(C), static_cast<uint32_t>(t), purpose, index);
-            const uint32_t sel0 = rdlane_u(w.w0, 0), sel1 = rdlane_u(w.w1, 0);
+            const int base = (t - tb) * B;
+            const uint32_t sel0 = rdlane_u(wb.w0, base), sel1 = rdlane_u(wb.w1, base);
             const int jl = static_cast<int>(pick(sel0, static_cast<uint32_t>(c.nc)));
             const bool rotate = ORI && P.p_rot > 0.0 && u01(sel1) < P.p_rot;
             c.jslot = c.start + jl;
@@ -826,7 +832,7 @@ __device__ __forceinline__ void phase_body(const Params& P, const WorkG& W, int 
             double qn[4] = {qj.x, qj.y, qj.z, qj.w};
             if (!rotate) {
                 double xs[3] = {pj.x, pj.y, pj.z};
-                uint32_t tw[3] = {rdlane_u(w.w0, 1), rdlane_u(w.w1, 1), rdlane_u(w.w2, 1)};
+                uint32_t tw[3] = {rdlane_u(wb.w0, base + 1), rdlane_u(wb.w1, base + 1), rdlane_u(wb.w2, base + 1)};
                 double xo[3];
 #pragma unroll
                 for (int ax3 = 0; ax3 < 3; ++ax3) {
@@ -839,30 +845,20 @@ __device__ __forceinline__ void phase_body(const Params& P, const WorkG& W, int 
                 }
                 xn = v3(xo[0], xo[1], xo[2]);
             } else {
-                // first accepted 4-ball candidate over the ROT blocks
+                // the first accepted 4-ball candidate of the trial's ROT stream
+                // (indices 0 .. 255, 64 per pass, in index order)
                 double m[4];
-                bool acc = (lane >= 32) && ball4(w, m);
-                unsigned long long am = __ballot(acc);
                 int src = -1;
                 uint32_t vw[4] = {0, 0, 0, 0};
-                if (am) {
-                    src = ffs64(am);
-                    vw[0] = rdlane_u(w.w0, src);
-                    vw[1] = rdlane_u(w.w1, src);
-                    vw[2] = rdlane_u(w.w2, src);
-                    vw[3] = rdlane_u(w.w3, src);
-                } else {
-                    for (uint32_t base = 32; base < 256u && src < 0; base += 64) {
-                        Words r = draw(P, static_cast<uint32_t>(C), static_cast<uint32_t>(t), kRot, base + lane);
-                        bool ok = (base + lane < 256u) && ball4(r, m);
-                        unsigned long long om = __ballot(ok);
-                        if (om) {
-                            src = ffs64(om);
-                            vw[0] = rdlane_u(r.w0, src);
-                            vw[1] = rdlane_u(r.w1, src);
-                            vw[2] = rdlane_u(r.w2, src);
-                            vw[3] = rdlane_u(r.w3, src);
-                        }
+                for (uint32_t rb = 0; rb < 256u && src < 0; rb += 64) {
+                    Words r = draw(P, static_cast<uint32_t>(C), static_cast<uint32_t>(t), kRot, rb + lane);
+                    unsigned long long om = __ballot(ball4(r, m));
+                    if (om) {
+                        src = ffs64(om);
+                        vw[0] = rdlane_u(r.w0, src);
+                        vw[1] = rdlane_u(r.w1, src);
+                        vw[2] = rdlane_u(r.w2, src);
+                        vw[3] = rdlane_u(r.w3, src);
                     }
                 }
                 if (src >= 0) {
@@ -942,20 +938,21 @@ __device__ __forceinline__ void phase_body(const Params& P, const WorkG& W, int 
                     o.reason = 2;
                 } else if (P.has_dep) {
                     // --- Poisson number of depletants in V_0 ------------------------
-                    int kc = 0;
-                    if (lane >= 3 && lane < 32 && lane - 3 < P.n_chunks) kc = poisson_guided(sF, sG, u52(w.w0, w.w1));
-                    for (int base = 29; base < P.n_chunks; base += 64) {
-                        int ci = base + lane;
+                    // chunk counts sit in lanes base + 3 .. base + 2 + n_chunks; chunks past
+                    // lane 63 (more than 61 of them: then one trial per batch) are drawn here
+                    int kx = (lane >= base + 3 && lane < base + 3 + P.n_chunks) ? kcb : 0;
+                    for (int cbase = 61; cbase < P.n_chunks; cbase += 64) {
+                        int ci = cbase + lane;
                         if (ci < P.n_chunks) {
                             Words pw = draw(P, static_cast<uint32_t>(C), static_cast<uint32_t>(t), kPoisson,
                                             static_cast<uint32_t>(ci));
-                            kc += poisson_guided(sF, sG, u52(pw.w0, pw.w1));
+                            kx += poisson_guided(sF, sG, u52(pw.w0, pw.w1));
                         }
                     }
-                    // chunk counts sit in lanes 3 .. 3 + n_chunks - 1 (more chunks: in every lane)
-                    const uint32_t Np = static_cast<uint32_t>(P.n_chunks <= 8 ? lanes_sum(kc, 3, P.n_chunks) : wave_sum(kc));
+                    const uint32_t Np =
+                        static_cast<uint32_t>(P.n_chunks <= 8 ? lanes_sum(kcb, base + 3, P.n_chunks) : wave_sum(kx));
                     o.n_dep = Np;
-                    const double au = u52(rdlane_u(w.w0, 2), rdlane_u(w.w1, 2));
+                    const double au = u52(rdlane_u(wb.w0, base + 2), rdlane_u(wb.w1, base + 2));
                     const Vec3 Dold = v3(mi(P, pj.x - xn.x), mi(P, pj.y - xn.y), mi(P, pj.z - xn.z));
                     const Vec3 zero3 = v3(0.0, 0.0, 0.0);
                     double ratio = 1.0;
