@@ -59,19 +59,19 @@ def shell_ops_per_check(R0: float, r_i: float) -> float:
 # busy with active lanes (rocprofv3 VALUBusy x VALUUtilization).  The HBM bytes
 # per launch are FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the factors a plain
 # 256 MiB device copy reads off the same counters).
-PROFILED_KERNEL_DIGEST = "878f2af8207f6af4"
+PROFILED_KERNEL_DIGEST = "1b0bcdc5dded27aa"
 PROFILE = {
     # 1,048,576 spheres, ball region, 212.05 resolved checks per move
-    "sphere": {"a_dep": 175.71, "b_move": 13732.1, "valu_instr_per_move": 1195.6, "valu_busy": 66.71,
-               "valu_utilization": 66.64, "traffic_bytes_per_launch": 67605942},
+    "sphere": {"a_dep": 175.00, "b_move": 15180.4, "valu_instr_per_move": 1231.5, "valu_busy": 77.57,
+               "valu_utilization": 66.35, "traffic_bytes_per_launch": 65249520},
     # 16,384 hemispheres at eta_r 0.4, 72.31 resolved checks per move
-    "hemisphere": {"a_dep": 393.34, "b_move": 34580.2, "valu_instr_per_move": 2097.7, "valu_busy": 12.60,
-                   "valu_utilization": 46.94, "traffic_bytes_per_launch": 4443985},
+    "hemisphere": {"a_dep": 393.58, "b_move": 34067.5, "valu_instr_per_move": 2099.3, "valu_busy": 12.69,
+                   "valu_utilization": 46.54, "traffic_bytes_per_launch": 4395867},
     # 256 swept-disk replicas, both launch groups of a phase, 56.50 resolved checks per move
-    "discoid": {"a_dep": 480.02, "b_move": 29311.9, "valu_instr_per_move": 2307.1,
-                "valu_busy": {"replicas of two cells per axis": 0.82, "the others": 42.99},
-                "valu_utilization": {"replicas of two cells per axis": 35.11, "the others": 38.27},
-                "traffic_bytes_per_phase": 93847843},
+    "discoid": {"a_dep": 480.09, "b_move": 29100.9, "valu_instr_per_move": 2306.1,
+                "valu_busy": {"replicas of two cells per axis": 0.83, "the others": 43.51},
+                "valu_utilization": {"replicas of two cells per axis": 35.06, "the others": 38.14},
+                "traffic_bytes_per_phase": 85921754},
 }
 
 

@@ -236,8 +236,8 @@ int hpmc_sweep_static(hpmc_sim* sim, int n_sweeps, hpmc_counters* out);
  * random draw is keyed by sweep, cell, round and purpose, not by thread), only
  * the speed.  Zero fields mean the default. */
 typedef struct hpmc_tuning {
-    int32_t cells_per_wave;  /* spheres: active cells per wave, 1..64 (default 16) */
-    int32_t waves_per_block; /* 1, 2 or 4 (default 4; lowered to what the LDS holds) */
+    int32_t cells_per_wave;  /* spheres: active cells per wave, 1..64 (default 8) */
+    int32_t waves_per_block; /* 1, 2 or 4 (default 1 for spheres, 4 for oriented shapes; lowered to what the LDS holds) */
     int32_t max_waves;       /* oriented shapes: waves of the grid-stride launch, >= 1 (default 8192) */
     int32_t candidates;      /* hpmc_autotune: configurations timed */
     double best_ms;          /* hpmc_autotune: phase-kernel ms per sweep of the chosen shape */
@@ -251,7 +251,7 @@ typedef struct hpmc_tuning {
 int hpmc_set_tuning(hpmc_sim* sim, const hpmc_tuning* tuning);
 
 /* Autotuner: time candidate launch shapes (spheres: cells per wave in
- * {4, 8, 10, 12, 16, 32, 64} x waves per block in {1, 2, 4}; oriented shapes: waves
+ * {4, 6, 8, 10, 12, 16, 32, 64} x waves per block in {1, 2, 4}; oriented shapes: waves
  * per block x wave count in {1024 .. 32768}) on a copy of the current state,
  * `sweeps` timed sweeps each after one untimed, keep the fastest, and report
  * it in *out (may be NULL).  The handle's state and sweep index are left as
@@ -300,6 +300,15 @@ int hpmc_sweep_batch(hpmc_sim* const* sims, int n_sims, void* batch_ws, size_t b
  * its state and its previous launch shape. */
 int hpmc_autotune_batch(hpmc_sim* const* sims, int n_sims, void* batch_ws, size_t ws_bytes, void* scratch,
                         size_t scratch_bytes, int sweeps, hpmc_tuning* out);
+
+/* The Poisson count of one depletant chunk (Sec. III.B, step 2: the number of
+ * depletants in V_0 is a sum of chunk counts) that the sweeps draw for the
+ * 52-bit uniform u in (0, 1), evaluated on the host from the table the device
+ * uses: the smallest k with P(N <= k) >= u for the chunk mean of the current
+ * fugacity, or 1023 when the running sum of the table stays below u.  For
+ * inspection and tests; no device work.  Errors: EINVAL (u outside (0, 1)),
+ * ESTATE (no shape set yet, so no table). */
+int hpmc_poisson_draw(const hpmc_sim* sim, double u, int32_t* k);
 
 /* Observables of the current state (host out, synchronous):
  *   HPMC_OBS_GR: out[0..n_bins) = g(r) of reference-point distances on

@@ -53,6 +53,7 @@ EXPORTS = (
     "hpmc_set_tuning",
     "hpmc_autotune",
     "hpmc_autotune_batch",
+    "hpmc_poisson_draw",
 )
 
 COUNTERS = (
@@ -147,6 +148,7 @@ def lib():
         L.hpmc_sweep_batch.argtypes = [ctypes.POINTER(vp), cint, vp, ctypes.c_size_t, cint, ctypes.POINTER(_Counters)]
         L.hpmc_set_tuning.argtypes = [vp, ctypes.POINTER(_Tuning)]
         L.hpmc_autotune.argtypes = [vp, vp, ctypes.c_size_t, cint, ctypes.POINTER(_Tuning)]
+        L.hpmc_poisson_draw.argtypes = [vp, dbl, ctypes.POINTER(ctypes.c_int32)]
         L.hpmc_autotune_batch.argtypes = [ctypes.POINTER(vp), cint, vp, ctypes.c_size_t, vp, ctypes.c_size_t, cint,
                                           ctypes.POINTER(_Tuning)]
         for name in EXPORTS:
@@ -206,6 +208,13 @@ class Sim:
 
     def set_fugacity(self, z_p: float, d_dep: float, n_trial: int = 0):
         self._chk(lib().hpmc_set_fugacity(self._h, float(z_p), float(d_dep), int(n_trial)), "set_fugacity")
+
+    def poisson_draw(self, u: float) -> int:
+        """The depletant chunk count the sweeps draw for the 52-bit uniform u
+        (hpmc_poisson_draw: host evaluation of the device's table)."""
+        k = ctypes.c_int32(0)
+        self._chk(lib().hpmc_poisson_draw(self._h, float(u), ctypes.byref(k)), "poisson_draw")
+        return int(k.value)
 
     def set_moves(self, d_trans: float, a_rot: float = 0.0, p_rot: float = 0.0, n_select: int = 1):
         self._chk(lib().hpmc_set_moves(self._h, float(d_trans), float(a_rot), float(p_rot), int(n_select)),

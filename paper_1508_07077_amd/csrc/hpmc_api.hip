@@ -52,8 +52,10 @@ struct hpmc_sim {
     double w = 0, inv_w = 0, R0 = 0, lambda = 0, lambda_c = 0, s_ball = 0;
     double r_inner = 0, span = 0;  // shell region: inner radius, R0 - r_inner
     int n_chunks = 1;
-    double F[kPoissonK];
-    int G[kGuide];  // guide: first k with F[k] >= i / kGuide
+    double F[kPoissonC];  // compact inverse-CDF table of the chunk mean (see kernels.hpp)
+    int G[kGuide];        // guide: first compact index with F >= i / kGuide
+    int pk_min = 0, pk_n = 1;
+    int table_set = 0;    // F and G hold the table of the current parameters
     int F_dirty = 1;
     // state and workspace
     double* pos = nullptr;
@@ -153,13 +155,29 @@ int derive(hpmc_sim* s)
     if (m < 1) m = 1;
     s->n_chunks = m;
     s->lambda_c = s->lambda / static_cast<double>(m);
+    // the full table F[k] = P(N <= k) by forward recursion, sentinel last
+    std::vector<double> full(kPoissonK);
     double P = exp(-s->lambda_c);
-    s->F[0] = P;
+    full[0] = P;
     for (int k = 1; k < kPoissonK - 1; ++k) {
         P = P * (s->lambda_c / static_cast<double>(k));
-        s->F[k] = s->F[k - 1] + P;
+        full[k] = full[k - 1] + P;
     }
-    s->F[kPoissonK - 1] = 2.0;
+    full[kPoissonK - 1] = 2.0;
+    // the entries a 52-bit uniform can stop at (kernels.hpp), then the sentinel
+    const double umin = ldexp(1.0, -53), umax = 1.0 - ldexp(1.0, -53);
+    int kmin = 0;
+    while (full[static_cast<size_t>(kmin)] < umin) ++kmin;
+    int kend = kmin;
+    while (kend < kPoissonK - 2 && full[static_cast<size_t>(kend)] < umax &&
+           full[static_cast<size_t>(kend) + 1] != full[static_cast<size_t>(kend)])
+        ++kend;
+    const int nc = kend - kmin + 1;
+    if (nc + 1 > kPoissonC) return fail(s, HPMC_EINVAL, "Poisson table of the chunk mean exceeds its capacity");
+    for (int i = 0; i < kPoissonC; ++i) s->F[i] = i < nc ? full[static_cast<size_t>(kmin + i)] : 2.0;
+    s->pk_min = kmin;
+    s->pk_n = nc;
+    s->table_set = 1;
     for (int i = 0, k = 0; i < kGuide; ++i) {
         double lev = static_cast<double>(i) / static_cast<double>(kGuide);
         while (s->F[k] < lev) ++k;
@@ -200,7 +218,7 @@ Layout layout(const hpmc_sim* s)
     l.order = take(N * 4);
     l.rpos = take(N * 32);
     l.rquat = take(s->S.oriented ? N * 32 : 0);
-    l.F = take(kPoissonK * 8 + kGuide * 4);
+    l.F = take(kPoissonC * 8 + kGuide * 4);
     l.grid = take(4 * 8);
     l.perm = take(8 * 4);
     l.counters = take(static_cast<size_t>(kCounterCopies) * kCounterStride * 8);
@@ -268,6 +286,8 @@ Params make_params(const hpmc_sim* s)
     P.n_select = s->n_select;
     P.n_trial = s->n_trial;
     P.n_chunks = s->n_chunks;
+    P.pk_min = s->pk_min;
+    P.pk_n = s->pk_n;
     P.has_dep = s->z_p > 0.0 ? 1 : 0;
     P.trace = s->trace;
     P.precision = s->precision;
@@ -328,7 +348,7 @@ Params make_params(const hpmc_sim* s)
         P.wave_lds = static_cast<int>(2 * o + kNumCounters * 8);
         P.list_cap = static_cast<int>(list_cap);
         P.geo_cap = static_cast<int>(geo_cap);
-        int wpb = s->tune_wpb ? s->tune_wpb : 4;
+        int wpb = s->tune_wpb ? s->tune_wpb : kSphereWpb;
         while (wpb > 1 && kTableLds + static_cast<size_t>(wpb) * P.wave_lds > lds_max) wpb >>= 1;
         P.waves_per_block = wpb;
         P.chunk = s->tune_chunk ? s->tune_chunk : kChunk;
@@ -426,8 +446,8 @@ std::vector<hpmc_tuning> tuning_candidates(bool oriented)
 {
     std::vector<hpmc_tuning> cand;
     if (!oriented) {
-        for (int c : {16, 4, 8, 10, 12, 32, 64})
-            for (int w : {4, 2, 1}) cand.push_back(hpmc_tuning{c, w, 0, 0, 0.0, 0.0});
+        for (int c : {kChunk, 4, 6, 10, 12, 16, 32, 64})
+            for (int w : {kSphereWpb, 2, 4}) cand.push_back(hpmc_tuning{c, w, 0, 0, 0.0, 0.0});
     } else {
         for (int m : {kMaxWaves, 1024, 2048, 4096, 16384, 32768})
             for (int w : {4, 2, 1}) cand.push_back(hpmc_tuning{0, w, m, 0, 0.0, 0.0});
@@ -510,7 +530,7 @@ int upload_table(hpmc_sim* s)
     if (!s->F_dirty) return HPMC_OK;
     hipError_t e = hipMemcpyAsync(s->W.F, s->F, sizeof(s->F), hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(s->W.F + kPoissonK, s->G, sizeof(s->G), hipMemcpyHostToDevice, s->stream);
+        e = hipMemcpyAsync(s->W.F + kPoissonC, s->G, sizeof(s->G), hipMemcpyHostToDevice, s->stream);
     if (e != hipSuccess) return hip_fail(s, e, "hipMemcpyAsync(table)");
     s->F_dirty = 0;
     return HPMC_OK;
@@ -572,7 +592,7 @@ int bind_static(hpmc_sim* s, Group& g, Work& W, unsigned long long** gather)
     s->static_desc.W = W;
     hipError_t e = hipMemcpyAsync(d_desc, &s->static_desc, sizeof(Desc), hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(W.F, s->F, sizeof(s->F), hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(W.F + kPoissonK, s->G, sizeof(s->G), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(W.F + kPoissonC, s->G, sizeof(s->G), hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess)
         e = launch_fill_int(reinterpret_cast<int*>(W.sweep_dev), 1, static_cast<int>(static_cast<uint32_t>(s->sweep)),
                             s->stream);
@@ -1424,6 +1444,15 @@ int hpmc_autotune_batch(hpmc_sim* const* sims, int n_sims, void* batch_ws, size_
         sims[i]->tune_waves = chosen[static_cast<size_t>(i)].max_waves;
         if (out) out[i] = chosen[static_cast<size_t>(i)];
     }
+    return HPMC_OK;
+}
+
+int hpmc_poisson_draw(const hpmc_sim* s, double u, int32_t* k)
+{
+    if (!s || !k) return HPMC_EINVAL;
+    if (!(u > 0.0 && u < 1.0)) return HPMC_EINVAL;
+    if (!s->table_set) return HPMC_ESTATE;
+    *k = poisson_compact_draw(s->F, s->G, u, s->pk_min, s->pk_n);
     return HPMC_OK;
 }
 

@@ -488,13 +488,10 @@ __device__ inline void cb_weights(const Params& P, const WorkG& W, const WaveCtx
     }
 }
 
-// smallest k with F[k] >= u, starting from the guide entry G[floor(256 u)]
 template <typename FP, typename GP>
-__device__ inline int poisson_guided(FP F, GP G, double u)
+__device__ inline int poisson_guided(FP F, GP G, double u, const Params& P)
 {
-    int k = G[static_cast<int>(u * 256.0)];
-    while (F[k] < u) ++k;
-    return k;
+    return poisson_compact_draw(F, G, u, P.pk_min, P.pk_n);
 }
 
 struct TrialOut {
@@ -723,9 +720,9 @@ __device__ __forceinline__ void phase_body(const Params& P, const WorkG& W, int 
     unsigned fb = 0;  // FP64 fallbacks of the guarded FP32 depletant tests (this lane)
     LAS unsigned char* smem = lds_base();
     LAS double* sF = (LAS double*)smem;
-    LAS int* sG = (LAS int*)(smem + kPoissonK * sizeof(double));
-    const GAS int* gG = (const GAS int*)(W.F + kPoissonK);
-    for (int i = threadIdx.x; i < kPoissonK; i += blockDim.x) sF[i] = W.F[i];
+    LAS int* sG = (LAS int*)(smem + kPoissonC * sizeof(double));
+    const GAS int* gG = (const GAS int*)(W.F + kPoissonC);
+    for (int i = threadIdx.x; i < kPoissonC; i += blockDim.x) sF[i] = W.F[i];
     for (int i = threadIdx.x; i < kGuide; i += blockDim.x) sG[i] = gG[i];
     __syncthreads();
 
@@ -817,7 +814,7 @@ __device__ __forceinline__ void phase_body(const Params& P, const WorkG& W, int 
                 const uint32_t index = q >= 3 ? static_cast<uint32_t>(q - 3) : 0u;
                 wb = draw(P, static_cast<uint32_t>(C), static_cast<uint32_t>(tb + tl), purpose, index);
                 kcb = 0;
-                if (valid && P.has_dep && q >= 3 && q - 3 < P.n_chunks) kcb = poisson_guided(sF, sG, u52(wb.w0, wb.w1));
+                if (valid && P.has_dep && q >= 3 && q - 3 < P.n_chunks) kcb = poisson_guided(sF, sG, u52(wb.w0, wb.w1), P);
             }
             const int base = (t - tb) * B;
             const uint32_t sel0 = rdlane_u(wb.w0, base), sel1 = rdlane_u(wb.w1, base);
@@ -946,7 +943,7 @@ __device__ __forceinline__ void phase_body(const Params& P, const WorkG& W, int 
                         if (ci < P.n_chunks) {
                             Words pw = draw(P, static_cast<uint32_t>(C), static_cast<uint32_t>(t), kPoisson,
                                             static_cast<uint32_t>(ci));
-                            kx += poisson_guided(sF, sG, u52(pw.w0, pw.w1));
+                            kx += poisson_guided(sF, sG, u52(pw.w0, pw.w1), P);
                         }
                     }
                     const uint32_t Np =
@@ -1190,9 +1187,9 @@ __device__ inline bool sphere_hit_lane(const Params& P, const WorkG& W, const Sp
 __device__ inline void load_table(const WorkG& W, LAS unsigned char* smem)
 {
     LAS double* sF = (LAS double*)smem;
-    LAS int* sG = (LAS int*)(smem + kPoissonK * sizeof(double));
-    const GAS int* gG = (const GAS int*)(W.F + kPoissonK);
-    for (int i = threadIdx.x; i < kPoissonK; i += blockDim.x) sF[i] = W.F[i];
+    LAS int* sG = (LAS int*)(smem + kPoissonC * sizeof(double));
+    const GAS int* gG = (const GAS int*)(W.F + kPoissonC);
+    for (int i = threadIdx.x; i < kPoissonC; i += blockDim.x) sF[i] = W.F[i];
     for (int i = threadIdx.x; i < kGuide; i += blockDim.x) sG[i] = gG[i];
 }
 
@@ -1202,7 +1199,7 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const WorkG& 
 {
     LAS unsigned char* smem = lds_base();
     LAS double* sF = (LAS double*)smem;
-    LAS int* sG = (LAS int*)(smem + kPoissonK * sizeof(double));
+    LAS int* sG = (LAS int*)(smem + kPoissonC * sizeof(double));
 
     const int lane = lane_id();
     const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));  // wave-uniform
@@ -1269,7 +1266,7 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const WorkG& 
         wb = draw(P, static_cast<uint32_t>(Cs), static_cast<uint32_t>(sl - o), purpose, index);
         jlb = static_cast<int>(pick(wb.w0, static_cast<uint32_t>(nk > 0 ? nk : 1)));
         kcb = 0;
-        if (valid && P.has_dep && q >= 3 && q - 3 < P.n_chunks) kcb = poisson_guided(sF, sG, u52(wb.w0, wb.w1));
+        if (valid && P.has_dep && q >= 3 && q - 3 < P.n_chunks) kcb = poisson_guided(sF, sG, u52(wb.w0, wb.w1), P);
     };
     // ranges of the stencil of chunk cell k (k < 0: none)
     auto ranges_of = [&](int k, int& es, int& ec) {
@@ -1373,7 +1370,7 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const WorkG& 
                             if (ci < P.n_chunks) {
                                 Words pw = draw(P, static_cast<uint32_t>(C), static_cast<uint32_t>(t), kPoisson,
                                                 static_cast<uint32_t>(ci));
-                                kx += poisson_guided(sF, sG, u52(pw.w0, pw.w1));
+                                kx += poisson_guided(sF, sG, u52(pw.w0, pw.w1), P);
                             }
                         }
                         const uint32_t Np = static_cast<uint32_t>(P.n_chunks <= 8 ? lanes_sum(kcb, base + 3, P.n_chunks)

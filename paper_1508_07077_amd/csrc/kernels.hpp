@@ -9,9 +9,29 @@
 
 namespace hpmc {
 
-constexpr int kPoissonK = 1024;      // inverse-CDF table length (last entry is a sentinel)
-constexpr int kGuide = 256;          // guide table: first k with F[k] >= i / 256
-constexpr int kTableLds = kPoissonK * 8 + kGuide * 4;
+// Poisson chunk counts: the inverse CDF F[k] = P(N <= k) of the chunk mean,
+// k < kPoissonK, whose last entry is a sentinel (a draw returns 0 .. K - 1).
+// Only k_min .. k_end can be returned for a 52-bit uniform u in
+// [2^-53, 1 - 2^-53]: F[k] < 2^-53 below k_min, and k_end is the first entry
+// >= 1 - 2^-53 or the start of the plateau where the running sum stops
+// growing (past it only the sentinel is reached).  The device keeps these
+// entries (at most 263 for chunk means up to 256) and a sentinel that stands
+// for K - 1: the same doubles, so the same draws, in a third of the LDS.
+constexpr int kPoissonK = 1024;
+constexpr int kPoissonC = 272;       // compact table capacity, sentinel included
+constexpr int kGuide = 256;          // guide table: first compact index with F >= i / 256
+constexpr int kTableLds = kPoissonC * 8 + kGuide * 4;
+
+// The chunk count of a 52-bit uniform u in (0, 1): the smallest k with
+// F[k] >= u, scanned from the guide entry G[floor(256 u)] of the compact table
+// (pk_n entries from k = pk_min, then the sentinel, which stands for K - 1).
+template <typename FP, typename GP>
+__host__ __device__ inline int poisson_compact_draw(FP F, GP G, double u, int pk_min, int pk_n)
+{
+    int k = G[static_cast<int>(u * 256.0)];
+    while (F[k] < u) ++k;
+    return k < pk_n ? pk_min + k : kPoissonK - 1;
+}
 constexpr int kCounterCopies = 256;  // spread copies of the counters (atomic contention)
 constexpr int kNumCounters = 13;
 constexpr int kCounterStride = 16;
@@ -70,6 +90,8 @@ struct Params {
     int active_cells;   // h^3
     // the phase launch: this replica's blocks are blk0 .. blk0 + nblk - 1 of the grid
     int blk0, nblk;
+    // compact Poisson table: entry i < pk_n is F[pk_min + i]; entry pk_n is the sentinel
+    int pk_min, pk_n;
 };
 
 // device workspace carved from the caller's buffer
@@ -82,7 +104,7 @@ struct Work {
     int* order;        // N: sorted slot -> particle
     double4* rpos;     // N: cell-ordered (x, y, z, particle index)
     double4* rquat;    // N: cell-ordered (w, x, y, z) (oriented shapes)
-    double* F;         // kPoissonK doubles, then kGuide ints
+    double* F;         // the compact Poisson table (kPoissonC doubles), then kGuide ints
     double* grid;      // shift g[3]
     int* perm;         // colour order [8]
     unsigned long long* counters;  // kCounterCopies x kCounterStride
@@ -139,7 +161,9 @@ size_t lds_limit();
 // wave; oriented shapes, one wave per active cell up to max_waves
 int phase_blocks(int kind, int active, int chunk, int wpb, int max_waves);
 
-constexpr int kChunk = 16;  // default active cells per wave of the sphere phase kernel
+constexpr int kChunk = 8;      // default active cells per wave of the sphere phase kernel
+constexpr int kSphereWpb = 1;  // default waves per workgroup of the sphere phase kernel: a wave's
+                               // slot and LDS are freed as soon as it ends
 constexpr int kMaxReplicaBlocks = 1024;  // phase blocks of one replica in a batched launch (waves loop over more)
 constexpr int kMaxWaves = 256 * 32;  // default wave count of the oriented phase launch
 constexpr int kSmallMaxActive = 32;  // spheres with at most this many active cells per phase and
