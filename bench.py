@@ -543,9 +543,9 @@ def bench_c2(args):
     dev_ms = 0.0
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        cs = b.sweep(1, counters=True)
-        dev_ms += cs[0]["sweep_ms"]
-        c = {k: sum(x[k] for x in cs) for k in cs[0] if k != "sweep_ms"}
+        cs = b.sweep(1, counters=True, as_array=True)
+        dev_ms += float(cs["sweep_ms"][0])
+        c = {k: int(cs[k].sum()) for k in hp.COUNTERS}
         btot = c if btot is None else {k: btot[k] + c[k] for k in btot}
     bdt = time.perf_counter() - t0
     broof = _roofline("hemisphere", profiled, btot["depletants_resolved"] / args.steps, btot["trials"] / args.steps,
@@ -595,10 +595,10 @@ def bench_c4(args):
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ts = time.perf_counter()
-        cs = b.sweep(1, counters=True)
+        cs = b.sweep(1, counters=True, as_array=True)
         lat.append((time.perf_counter() - ts) * 1e3)
-        dev_ms += cs[0]["sweep_ms"]
-        c = {k: sum(x[k] for x in cs) for k in cs[0] if k != "sweep_ms"}
+        dev_ms += float(cs["sweep_ms"][0])
+        c = {k: int(cs[k].sum()) for k in hp.COUNTERS}
         tot = c if tot is None else {k: tot[k] + c[k] for k in tot}
     dt = time.perf_counter() - t0
     roof = _roofline("discoid", kernel_digest() == PROFILED_KERNEL_DIGEST, tot["depletants_resolved"] / args.steps,

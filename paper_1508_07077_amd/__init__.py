@@ -93,6 +93,11 @@ class _Counters(ctypes.Structure):
                                                           ("sweep_ms", ctypes.c_double)]
 
 
+# the counter record as a numpy structured type (Batch.sweep(as_array=True))
+COUNTER_DTYPE = np.dtype([(f, "<u8") for f in COUNTERS] + [("phase_kernel_ms", "<f8"), ("sweep_ms", "<f8")])
+assert COUNTER_DTYPE.itemsize == ctypes.sizeof(_Counters)
+
+
 class _Tuning(ctypes.Structure):
     _fields_ = [
         ("cells_per_wave", ctypes.c_int32),
@@ -346,7 +351,10 @@ class Batch:
         self.sims = list(sims)
         self._handles = (ctypes.c_void_p * max(len(self.sims), 1))(*[s._h.value for s in self.sims])
 
-    def sweep(self, n_sweeps: int = 1, counters: bool = True):
+    def sweep(self, n_sweeps: int = 1, counters: bool = True, as_array: bool = False):
+        """Batched sweeps; with counters, one record per member: dicts, or with
+        as_array one numpy structured array (COUNTER_DTYPE), which costs no
+        per-field Python work for large batches."""
         n = len(self.sims)
         out = (_Counters * n)() if counters else None
         rc = lib().hpmc_sweep_batch(self._handles, n, ctypes.c_void_p(self.workspace.data_ptr()),
@@ -356,6 +364,8 @@ class Batch:
             raise HpmcError(rc, f"sweep_batch: {msg.decode() if msg else ''}")
         if not counters:
             return None
+        if as_array:
+            return np.frombuffer(out, dtype=COUNTER_DTYPE, count=n).copy()
         res = [{f: int(getattr(c, f)) for f in COUNTERS} for c in out]
         for d, c in zip(res, out):
             d["sweep_ms"] = float(c.sweep_ms)

@@ -4,7 +4,7 @@
 // Method: Glaser, Karas & Glotzer, arXiv:1508.07077.
 //   grid_kernel ............ random colour order and grid shift (Sec. III.E)
 //   bin / scan / scatter /
-//   sort / gather .......... cell list under the shifted checkerboard (Sec. III.E)
+//   rank / gather .......... cell list under the shifted checkerboard (Sec. III.E)
 //   phase_kernel ........... trial moves of one colour: proposal, hard overlap
 //                            (Eq. pacc), Poisson depletants in the circumsphere
 //                            (Sec. III.B step 2, Sec. III.C), classification and
@@ -657,22 +657,21 @@ __global__ void scatter_kernel(const Desc* __restrict__ D)
     W.order[W.cell_start[W.pcell[i]] + W.prank[i]] = i;
 }
 
-// members of each cell in ascending particle index (insertion sort; cells are small)
-__global__ void sort_kernel(const Desc* __restrict__ D)
+// Members of each cell in ascending particle index, the order trials select
+// from.  The scatter placed them in the order of their atomic ranks; each
+// particle's rank among its cell's members is the number of smaller indices
+// there, and a second scatter by these ranks sorts every cell at once (one
+// thread per particle, no serial pass over a cell).
+__global__ void rank_kernel(const Desc* __restrict__ D)
 {
     HPMC_REPLICA(D);
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= P.ncells) return;
-    int s = W.cell_start[c], e = W.cell_start[c + 1];
-    for (int i = s + 1; i < e; ++i) {
-        int v = W.order[i];
-        int j = i - 1;
-        while (j >= s && W.order[j] > v) {
-            W.order[j + 1] = W.order[j];
-            --j;
-        }
-        W.order[j + 1] = v;
-    }
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.N) return;
+    const int c = W.pcell[i];
+    const int s = W.cell_start[c], e = W.cell_start[c + 1];
+    int r = 0;
+    for (int k = s; k < e; ++k) r += W.order[k] < i ? 1 : 0;
+    W.prank[i] = r;
 }
 
 __global__ void gather_kernel(const Desc* __restrict__ D)
@@ -1650,18 +1649,15 @@ __global__ __launch_bounds__(64 * kSmallWaves) void sweep_small_kernel(const Des
         __syncthreads();
         for (int i = tid; i < P.N; i += nt) W.order[W.cell_start[W.pcell[i]] + W.prank[i]] = i;
         __syncthreads();
-        for (int c = tid; c < P.ncells; c += nt) {
-            int s0 = W.cell_start[c], e = W.cell_start[c + 1];
-            for (int i = s0 + 1; i < e; ++i) {
-                int v = W.order[i];
-                int j = i - 1;
-                while (j >= s0 && W.order[j] > v) {
-                    W.order[j + 1] = W.order[j];
-                    --j;
-                }
-                W.order[j + 1] = v;
-            }
+        // each cell's members in ascending index: ranks among the cell, then scatter again
+        for (int i = tid; i < P.N; i += nt) {
+            const int c = W.pcell[i];
+            int r = 0;
+            for (int k = W.cell_start[c]; k < W.cell_start[c + 1]; ++k) r += W.order[k] < i ? 1 : 0;
+            W.prank[i] = r;
         }
+        __syncthreads();
+        for (int i = tid; i < P.N; i += nt) W.order[W.cell_start[W.pcell[i]] + W.prank[i]] = i;
         __syncthreads();
         for (int q = tid; q < P.N; q += nt) {
             int i = W.order[q];
@@ -1986,7 +1982,8 @@ hipError_t launch_build_cells(const Group& g, bool with_grid, hipStream_t stream
     hipLaunchKernelGGL(scan_top_kernel, dim3(1, R), dim3(256), 0, stream, g.d);
     hipLaunchKernelGGL(scan_add_kernel, dim3(blocks_for(g.maxCells, 256), R), dim3(256), 0, stream, g.d);
     hipLaunchKernelGGL(scatter_kernel, dim3(blocks_for(g.maxN, 256), R), dim3(256), 0, stream, g.d);
-    hipLaunchKernelGGL(sort_kernel, dim3(blocks_for(g.maxCells, 256), R), dim3(256), 0, stream, g.d);
+    hipLaunchKernelGGL(rank_kernel, dim3(blocks_for(g.maxN, 256), R), dim3(256), 0, stream, g.d);
+    hipLaunchKernelGGL(scatter_kernel, dim3(blocks_for(g.maxN, 256), R), dim3(256), 0, stream, g.d);
     hipLaunchKernelGGL(gather_kernel, dim3(blocks_for(g.maxN, 256), R), dim3(256), 0, stream, g.d);
     return hipGetLastError();
 }

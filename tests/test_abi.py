@@ -123,3 +123,20 @@ def test_missing_library_fails_loudly(monkeypatch):
     monkeypatch.setattr(hp, "_lib", None)
     with pytest.raises(ImportError):
         hp.lib()
+
+
+def test_counter_array_layout(hp):
+    """Batch.sweep(as_array=True) reads the C counter records through
+    COUNTER_DTYPE: the same fields at the same offsets"""
+    import numpy as np
+
+    out = (hp._Counters * 3)()
+    for i, c in enumerate(out):
+        for j, f in enumerate(hp.COUNTERS):
+            setattr(c, f, 1000 * i + j)
+        c.phase_kernel_ms = 0.25 * i
+        c.sweep_ms = 0.5 + i
+    a = np.frombuffer(out, dtype=hp.COUNTER_DTYPE, count=3)
+    for i in range(3):
+        assert [int(a[f][i]) for f in hp.COUNTERS] == [1000 * i + j for j in range(len(hp.COUNTERS))]
+        assert a["phase_kernel_ms"][i] == 0.25 * i and a["sweep_ms"][i] == 0.5 + i
