@@ -106,3 +106,26 @@ def test_mixed_kinds_concurrent_groups(counters):
         assert np.array_equal(px, py)
         if qx is not None:
             assert np.array_equal(qx, qy)
+
+
+def test_counter_array_equals_the_records():
+    """Batch.sweep(as_array=True) returns the counters the dict form does:
+    two identical batches swept side by side"""
+    import paper_1508_07077_amd as hp
+
+    sps = _replicas(wl.SPHERE, 5, 41) + _replicas(wl.DISCOID, 4, 42)
+    a, b = [], []
+    for sp in sps:
+        pos, quat = sp.initial_state()
+        a.append(_handle(sp, pos, quat))
+        b.append(_handle(sp, pos, quat))
+    ba, bb = hp.Batch(a), hp.Batch(b)
+    for _ in range(3):
+        recs = ba.sweep(1, counters=True)
+        arr = bb.sweep(1, counters=True, as_array=True)
+        assert arr.shape == (len(sps),) and arr.dtype == hp.COUNTER_DTYPE
+        for r, x in zip(recs, arr):
+            assert all(r[f] == int(x[f]) for f in hp.COUNTERS)
+            assert x["sweep_ms"] > 0.0
+    for x in a + b:
+        x.close()
