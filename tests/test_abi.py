@@ -44,6 +44,9 @@ def test_library_exports_every_declared_symbol(hp):
         assert getattr(L, s) is not None
 
 
+ESTATE = -5
+
+
 def _handle(hp, n=64, L=6.9459):
     h = ctypes.c_void_p()
     assert hp.lib().hpmc_create(ctypes.byref(h), n, L, 1, 0, 0, None) == 0
@@ -140,3 +143,41 @@ def test_counter_array_layout(hp):
     for i in range(3):
         assert [int(a[f][i]) for f in hp.COUNTERS] == [1000 * i + j for j in range(len(hp.COUNTERS))]
         assert a["phase_kernel_ms"][i] == 0.25 * i and a["sweep_ms"][i] == 0.5 + i
+
+
+def test_batch_autotune_argument_checks(hp):
+    """hpmc_autotune_batch rejects a handle given twice, missing scratch and a
+    sweep count out of range before any device work, and handles without a
+    workspace or state with ESTATE"""
+    L = hp.lib()
+    hs = []
+    for _ in range(2):
+        h = ctypes.c_void_p()
+        assert L.hpmc_create(ctypes.byref(h), 100, 20.0, 1, 0, 0, None) == 0
+        assert L.hpmc_set_shape(h, 0, _dp([1.0]), 1) == 0
+        hs.append(h)
+    arr = (ctypes.c_void_p * 2)(hs[0].value, hs[0].value)
+    scratch = ctypes.c_void_p(1)
+    try:
+        assert L.hpmc_autotune_batch(arr, 2, None, 0, scratch, 1 << 20, 1, None) == -1  # handle twice
+        arr = (ctypes.c_void_p * 2)(hs[0].value, hs[1].value)
+        assert L.hpmc_autotune_batch(arr, 2, None, 0, None, 1 << 20, 1, None) == -1  # no scratch
+        assert L.hpmc_autotune_batch(arr, 2, None, 0, scratch, 1 << 20, 0, None) == -1  # sweeps < 1
+        assert L.hpmc_autotune_batch(arr, 2, None, 0, scratch, 1 << 20, 65, None) == -1  # sweeps > 64
+        assert L.hpmc_autotune_batch(arr, 0, None, 0, scratch, 1 << 20, 1, None) == -1
+        rc = L.hpmc_autotune_batch(arr, 2, None, 0, scratch, 1 << 20, 1, None)
+        assert rc == ESTATE  # no workspace yet
+    finally:
+        for h in hs:
+            L.hpmc_destroy(h)
+
+
+def test_poisson_draw_needs_a_table(hp):
+    L = hp.lib()
+    h = ctypes.c_void_p()
+    assert L.hpmc_create(ctypes.byref(h), 100, 20.0, 1, 0, 0, None) == 0
+    k = ctypes.c_int32(0)
+    try:
+        assert L.hpmc_poisson_draw(h, 0.5, ctypes.byref(k)) == ESTATE  # no shape, so no table yet
+    finally:
+        L.hpmc_destroy(h)
