@@ -393,7 +393,8 @@ Params make_params(const hpmc_sim* s)
 }
 
 // launch shape of a group of replicas (descriptors already on the device)
-Group make_group(const Desc* d, const hpmc_sim* const* sims, int n)
+// pars: the members' make_params results, or null to compute them here
+Group make_group(const Desc* d, const hpmc_sim* const* sims, int n, const Params* pars = nullptr)
 {
     Group g{};
     g.d = d;
@@ -406,7 +407,7 @@ Group make_group(const Desc* d, const hpmc_sim* const* sims, int n)
     g.max_waves = sims[0]->tune_waves ? sims[0]->tune_waves : kMaxWaves;
     size_t wave_lds = 0;
     for (int i = 0; i < n; ++i) {
-        Params P = make_params(sims[i]);
+        const Params P = pars ? pars[i] : make_params(sims[i]);
         g.maxN = std::max(g.maxN, P.N);
         g.maxCells = std::max(g.maxCells, P.ncells);
         g.maxActive = std::max(g.maxActive, P.active_cells);
@@ -455,10 +456,11 @@ std::vector<hpmc_tuning> tuning_candidates(bool oriented)
     return cand;
 }
 
-Desc make_desc(const hpmc_sim* s, int wpb, int chunk)
+// descriptor of a handle whose make_params result is P, at a launch shape
+Desc make_desc(const hpmc_sim* s, const Params& P, int wpb, int chunk)
 {
     Desc d{};
-    d.P = make_params(s);
+    d.P = P;
     d.P.waves_per_block = wpb;
     d.P.chunk = chunk;
     d.P.blk0 = 0;
@@ -471,7 +473,7 @@ Desc make_desc(const hpmc_sim* s, int wpb, int chunk)
 int sync_desc(hpmc_sim* s)
 {
     Params P = make_params(s);
-    Desc d = make_desc(s, P.waves_per_block, P.chunk);
+    Desc d = make_desc(s, P, P.waves_per_block, P.chunk);
     if (!s->desc_dirty && memcmp(&d, &s->desc, sizeof(Desc)) == 0) return HPMC_OK;
     s->desc = d;
     hipError_t e = hipMemcpyAsync(s->d_desc, &s->desc, sizeof(Desc), hipMemcpyHostToDevice, s->stream);
@@ -507,7 +509,8 @@ hipStream_t library_stream()
     return streams[dev];
 }
 
-int check_ready(hpmc_sim* s, bool need_state)
+// P_out: if not null, receives the handle's make_params result
+int check_ready(hpmc_sim* s, bool need_state, Params* P_out = nullptr)
 {
     if (!s->stream) s->stream = library_stream();
     if (!s->have_shape) return fail(s, HPMC_ESTATE, "shape not set");
@@ -522,6 +525,7 @@ int check_ready(hpmc_sim* s, bool need_state)
         if (r != HPMC_OK) return r;
         s->sweep_dev_stale = 0;
     }
+    if (P_out) *P_out = P;
     return HPMC_OK;
 }
 
@@ -588,7 +592,7 @@ int bind_static(hpmc_sim* s, Group& g, Work& W, unsigned long long** gather)
     if (r != HPMC_OK) return r;
     Desc* d_desc = nullptr;
     W = carve(s, base, &d_desc, gather);
-    s->static_desc = make_desc(s, P.waves_per_block, P.chunk);
+    s->static_desc = make_desc(s, P, P.waves_per_block, P.chunk);
     s->static_desc.W = W;
     hipError_t e = hipMemcpyAsync(d_desc, &s->static_desc, sizeof(Desc), hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(W.F, s->F, sizeof(s->F), hipMemcpyHostToDevice, s->stream);
@@ -1203,9 +1207,11 @@ int hpmc_sweep_batch(hpmc_sim* const* sims, int n_sims, void* batch_ws, size_t b
         if (sims[0]) fail(sims[0], HPMC_ENOMEM, "batch workspace missing or too small");
         return HPMC_ENOMEM;
     }
+    // every replica's derived parameters, once per call
+    std::vector<Params> par(static_cast<size_t>(n_sims));
     for (int i = 0; i < n_sims; ++i) {
         if (!sims[i]) return HPMC_EINVAL;
-        int r = check_ready(sims[i], true);
+        int r = check_ready(sims[i], true, &par[static_cast<size_t>(i)]);
         if (r == HPMC_OK) r = upload_table(sims[i]);
         if (r != HPMC_OK) return r;
         if (sims[i]->trace) return fail(sims[i], HPMC_EINVAL, "tracing is per handle; disable it for batched sweeps");
@@ -1217,8 +1223,6 @@ int hpmc_sweep_batch(hpmc_sim* const* sims, int n_sims, void* batch_ws, size_t b
     Desc* d_all = reinterpret_cast<Desc*>(base + bl.desc);
     int* d_brep = reinterpret_cast<int*>(base + bl.brep);
     unsigned long long* d_gather = reinterpret_cast<unsigned long long*>(base + bl.gather);
-    std::vector<Params> par(static_cast<size_t>(n_sims));
-    for (int i = 0; i < n_sims; ++i) par[static_cast<size_t>(i)] = make_params(sims[i]);
     std::vector<int> cl(static_cast<size_t>(n_sims));
     for (int i = 0; i < n_sims; ++i) cl[static_cast<size_t>(i)] = batch_class(sims[i], par[static_cast<size_t>(i)]);
     auto cls = [&](int i) { return cl[static_cast<size_t>(i)]; };
@@ -1243,12 +1247,16 @@ int hpmc_sweep_batch(hpmc_sim* const* sims, int n_sims, void* batch_ws, size_t b
         size_t e = b;
         while (e < order.size() && cls(order[e]) == cls(order[b])) ++e;
         std::vector<const hpmc_sim*> members;
-        for (size_t q = b; q < e; ++q) members.push_back(sims[order[q]]);
-        Group g = make_group(d_all + b, members.data(), static_cast<int>(members.size()));
+        std::vector<Params> mpar;
+        for (size_t q = b; q < e; ++q) {
+            members.push_back(sims[order[q]]);
+            mpar.push_back(par[static_cast<size_t>(order[q])]);
+        }
+        Group g = make_group(d_all + b, members.data(), static_cast<int>(members.size()), mpar.data());
         // flat phase launch: each replica's own blocks, one after another
         const size_t first_block = brep.size();
         for (size_t q = b; q < e; ++q) {
-            Desc d = make_desc(sims[order[q]], g.wpb, g.chunk);
+            Desc d = make_desc(sims[order[q]], par[static_cast<size_t>(order[q])], g.wpb, g.chunk);
             if (g.kind == kSphere) {
                 // a wave takes one chunk of cells: a large box takes larger chunks
                 while (d.P.nblk > kMaxReplicaBlocks && d.P.chunk < 64) {
@@ -1342,10 +1350,11 @@ int hpmc_autotune_batch(hpmc_sim* const* sims, int n_sims, void* batch_ws, size_
     size_t need = 0;
     for (int i = 0; i < n_sims; ++i) {
         hpmc_sim* x = sims[i];
-        int r = check_ready(x, true);
+        Params Px;
+        int r = check_ready(x, true, &Px);
         if (r != HPMC_OK) return r;
         if (x->trace) return fail(x, HPMC_EINVAL, "tracing is per handle; disable it for batched sweeps");
-        cl[static_cast<size_t>(i)] = batch_class(x, make_params(x));
+        cl[static_cast<size_t>(i)] = batch_class(x, Px);
         off[static_cast<size_t>(i)] = need;
         const size_t N = static_cast<size_t>(x->N);
         need += (N * 3 * sizeof(double) + (x->S.oriented ? N * 4 * sizeof(double) : 0) + 255) / 256 * 256;
