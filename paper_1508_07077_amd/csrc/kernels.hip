@@ -12,12 +12,16 @@
 //                            configurational bias (Sec. III.D, Eq. pacc_cb)
 //   scatter_back ........... cell-ordered records back to the caller's SoA state
 //
-// Mapping: one wavefront per active cell.  Lanes draw one Philox block each
-// (two ball candidates); accepted candidates get their depletant index from a
-// ballot + popcount prefix, so the wave resolves ~67 depletants per pass in
-// exactly the serial order.  Depletants that survive the cheap old-pose test
-// (a few per move) are tested against the cell stencil lane-per-neighbour,
-// and CB re-insertions of a blocking depletant run lane-per-trial.
+// Mapping: one wavefront runs the active cells of a chunk one after another
+// (spheres: 8 cells by default, one wave per workgroup; oriented shapes: one
+// cell at a time).  The draws of a cell's trials that depend on the random
+// streams alone come from one Philox pass for several trials.  In a
+// depletant pass, lanes draw one Philox block each (two ball candidates);
+// accepted candidates get their depletant index from a ballot + popcount
+// prefix, so the wave resolves ~67 depletants per pass in exactly the serial
+// order.  Depletants that survive the cheap old-pose test (a few per move) are
+// tested against the cell stencil lane-per-neighbour, and CB re-insertions of
+// a blocking depletant run lane-per-trial.
 #include <hip/hip_runtime.h>
 
 #include <mutex>

@@ -129,7 +129,7 @@ struct Group {
     int nblocks;      // phase launches: blocks of the grid
     int nrep;
     int kind;
-    int precision;  // 0 FP64, 1 FP32 with the FP64 guard band (sphere depletant tests)
+    int precision;  // 0 FP64, 1 FP32 depletant tests with the FP64 guard band
     int shell;      // insertion region: 0 ball, 1 shell (common to the group)
     int maxN, maxCells, maxActive;
     int wpb;        // waves per block of the phase kernel (common to the group)
