@@ -129,3 +129,35 @@ def test_counter_array_equals_the_records():
             assert x["sweep_ms"] > 0.0
     for x in a + b:
         x.close()
+
+
+def test_replicas_past_the_block_cap_equal_alone():
+    """A replica that needs more than the 1,024 blocks a batched phase launch
+    gives it: 16,384 hemispheres (1,728 active cells) at one wave per
+    workgroup, whose waves then take several cells in turn, and 60,000
+    spheres (9,261 active cells) at 8 cells per one-wave workgroup,
+    whose chunk of cells grows instead.  Both sweep exactly as alone."""
+    import paper_1508_07077_amd as hp
+
+    hem = wl.StatePoint(wl.HEMISPHERE, (1.0,), 16384, 0.20, 0.15, 0.3, d_trans=0.05, a_rot=0.05, p_rot=0.5,
+                        seed=51, replica_id=1)
+    sph = wl.StatePoint(wl.SPHERE, (1.0,), 60000, 0.30, 0.10, 0.3, n_trial=2, d_trans=0.01, seed=52, replica_id=2)
+    sps = [hem, sph]
+    states = [sp.initial_state() for sp in sps]
+    batch_sims = [_handle(sp, p, q) for sp, (p, q) in zip(sps, states)]
+    alone = [_handle(sp, p, q) for sp, (p, q) in zip(sps, states)]
+    for g in batch_sims + alone:
+        g.set_tuning(8 if g.kind == wl.SPHERE else 0, 1, 0)
+    cb = hp.Batch(batch_sims).sweep(2)
+    for g, sp, c in zip(alone, sps, cb):
+        ca = g.sweep(2)
+        for k in ("trials", "accepts", "depletants_drawn", "depletants_resolved", "rej_overlap", "cb_trials"):
+            assert ca[k] == c[k], (sp.name, k)
+    for g, h in zip(alone, batch_sims):
+        pa, qa, sa = g.get_state()
+        pb, qb, sb = h.get_state()
+        assert sa == sb == 2 and np.array_equal(pa, pb)
+        if qa is not None:
+            assert np.array_equal(qa, qb)
+    for g in batch_sims + alone:
+        g.close()
