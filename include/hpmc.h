@@ -265,10 +265,16 @@ int hpmc_batch_workspace_bytes(int n_sims, size_t* bytes);
 
 /* Run n_sweeps sweeps of n_sims independent handles (replicas of uneven size,
  * density and fugacity; growth path of the paper's parallel scheme,
- * Sec. III.E) in shared launches: every kernel covers all replicas of one
- * shape kind, indexing them by the grid's second dimension.  Each handle keeps
- * its own state, workspace and random streams, so every replica's trajectory
- * is identical to what hpmc_sweep gives it alone.  All handles must be ready
+ * Sec. III.E) in shared launches.  Replicas of one shape kind, precision,
+ * insertion region and box class form a launch group (groups run on up to
+ * four streams); a group's cell-list kernels index its replicas by the grid's
+ * second dimension, and each of its phase launches holds only blocks with
+ * work, every replica's blocks one after another (at most 1024 per replica;
+ * past that an oriented replica's waves take several cells in turn and a
+ * sphere replica takes larger chunks of cells, up to 64 per wave, else
+ * ECAPACITY).  Each handle keeps its own state, workspace and random streams,
+ * so every replica's trajectory is identical to what hpmc_sweep gives it
+ * alone.  All handles must be ready
  * (shape, workspace, state) and use the stream of sims[0]; tracing must be
  * off.  batch_ws: device scratch of hpmc_batch_workspace_bytes(n_sims); the
  * descriptors are copied into it on the stream from pinned host staging
