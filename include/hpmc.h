@@ -23,8 +23,8 @@
  *     caller; the library owns no device memory.  "host" pointers are read or
  *     written synchronously.
  *   - All device work is enqueued on the stream given to hpmc_create (NULL =
- *     the default stream).  A handle is not thread-safe; handles are
- *     independent of each other.
+ *     the library's own blocking stream for the device, see hpmc_create).  A
+ *     handle is not thread-safe; handles are independent of each other.
  *   - Positions are SoA [3][n] doubles (x row, y row, z row) in [0, L];
  *     orientations are SoA [4][n] unit quaternions (w, x, y, z rows).
  */
