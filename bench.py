@@ -120,6 +120,26 @@ def parse():
     return ap.parse_args()
 
 
+def _copy_gbps(torch, n_bytes: int = 1 << 30, reps: int = 5) -> float:
+    """HBM bandwidth of a plain device-to-device copy (bytes read + written per
+    second, best of `reps`), the practical bound beside the 8 TB/s peak"""
+    src = torch.ones(n_bytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * n_bytes / (best * 1e-3) / 1e9
+
+
 def _cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -295,6 +315,11 @@ def main():
         "fp32_guarded": fp32,
         "launch_tuning": tuning,
     }
+    roof = line["roofline"]
+    if roof.get("traffic"):
+        # the phase kernel's HBM rate beside a plain copy's (not the bound: the kernel is VALU-bound)
+        roof["hbm"] = {"achieved_gbps": roof["traffic"] / avg_phase_s / 1e9, "copy_gbps": _copy_gbps(torch),
+                       "peak_gbps": 8000.0}
     if args.cpu_seconds > 0:
         line["cpu_baseline"] = cpu_baseline(lambda n: wl.c3_spheres_large(n=n, d_trans=sp.d_trans), args.cpu_n,
                                             args.cpu_seconds)
