@@ -206,6 +206,53 @@ def cpu_baseline(sp_factory, n_sample: int, seconds: float):
     }
 
 
+def _oracle_threads() -> int:
+    threads = max(1, int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    return min(threads, os.cpu_count() or 1)
+
+
+def cpu_baseline_states(sps, sweeps: int, seconds: float, what: str, melt: int = 5):
+    """The oracle as it is (OpenMP over the active cells of a phase on the
+    cores it may use) on a bounded sample of a workload's state points: each
+    from its start, `melt` untimed sweeps at zero fugacity, then up to
+    `sweeps` timed sweeps, until `seconds` of timed work have passed."""
+    from oracle import pyoracle
+
+    threads = _oracle_threads()
+    trials = resolved = 0
+    timed = 0.0
+    done = []
+    for sp in sps:
+        pos, quat = sp.initial_state()
+        o = pyoracle.OracleSim(sp.n, sp.L, sp.seed, sp.replica_id)
+        o.set_shape(sp.kind, sp.params)
+        o.set_threads(threads)
+        o.set_fugacity(0.0, sp.d_dep, 0)
+        o.set_moves(0.1, 0.1 if sp.kind != pyoracle.SPHERE else 0.0, sp.p_rot)
+        o.set_state(pos, quat)
+        if melt:
+            o.sweep(melt)
+        o.set_fugacity(sp.z_p, sp.d_dep, sp.n_trial)
+        o.set_moves(sp.d_trans, sp.a_rot, sp.p_rot)
+        n = 0
+        t0 = time.perf_counter()
+        while n < sweeps and timed + (time.perf_counter() - t0) < seconds:
+            c = o.sweep(1)
+            trials += c["trials"]
+            resolved += c["depletants_resolved"]
+            n += 1
+        timed += time.perf_counter() - t0
+        done.append(n)
+        if timed >= seconds:
+            break
+    return {"value": trials / timed, "unit": "colloid trial moves/s", "depletant_checks_per_s": resolved / timed,
+            "cores": threads, "kind": "oracle",
+            "sample": f"{what}: {len(done)} state point(s), {sum(done)} timed sweep(s) in all "
+                      f"({', '.join(str(x) for x in done)}), after {melt} untimed zero-fugacity sweeps each, "
+                      f"{threads} OpenMP threads, {timed:.1f} s",
+            "nproc": os.cpu_count()}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -480,11 +527,13 @@ def bench_c1(args):
         c = sim.sweep(1, counters=True)
         lat.append((time.perf_counter() - ts) * 1e3)
         tot = c if tot is None else {k: tot[k] + c[k] for k in tot}
+    extra = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+             "latency_note": "per-sweep latency of timed single-sweep calls (launch + counter readback)"}
+    if args.cpu_seconds > 0:
+        extra["cpu_baseline"] = cpu_baseline_states([sp], 1000, args.cpu_seconds, "the same 64-sphere box, 1000 sweeps")
     return _line(1000 * sp.n / dt, {"depletants_resolved": tot["depletants_resolved"] * 1000 / 200,
                                      "accepts": tot["accepts"], "trials": tot["trials"]}, dt, 1000, 10,
-                 "hard spheres N=64 phi_c=0.10 q=0.25 eta_r=0.10 delta=0.1, 1000 sweeps (graph replay)",
-                 {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                  "latency_note": "per-sweep latency of timed single-sweep calls (launch + counter readback)"})
+                 "hard spheres N=64 phi_c=0.10 q=0.25 eta_r=0.10 delta=0.1, 1000 sweeps (graph replay)", extra)
 
 
 def bench_c2(args):
@@ -592,6 +641,10 @@ def bench_c2(args):
                # one state point alone, per launch (the one with the most depletant work)
                "roofline_one_state_point": roofs.get("0.4", roofs[max(roofs)]) if roofs else None})
     d.pop("acceptance")
+    if args.cpu_seconds > 0:
+        etas = [float(x) for x in args.eta.split(",")]
+        d["cpu_baseline"] = cpu_baseline_states([wl.c2_hemispheres(e) for e in etas], 5, args.cpu_seconds,
+                                                "the same 16,384-hemisphere boxes, 5 sweeps per eta_r")
     return d
 
 
@@ -657,7 +710,10 @@ def bench_c4(args):
                  "phi_c U[0.05,0.45], eta_r U[0,0.5], q=0.2, one launch per kernel for all replicas",
                  {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                   "replicas": len(sps), "launch_tuning": tuning, "graph_replay": graph, "one_at_a_time": alone,
-                  "roofline": roof})
+                  "roofline": roof,
+                  "cpu_baseline": cpu_baseline_states(sps[::32], 5, args.cpu_seconds,
+                                                      "8 of the 256 replicas (every 32nd), 5 sweeps each")
+                  if args.cpu_seconds > 0 else None})
 
 
 def bench_c5(args):
@@ -721,6 +777,9 @@ def bench_c5(args):
         "hbm_budget": srv.budget,
         "latency_note": "per request, arrival to observables returned",
         "capacity": cap,
+        "cpu_baseline": cpu_baseline_states(specs[:10], 100, args.cpu_seconds,
+                                            "the first 10 requests of the stream, 100 sweeps each (sweeps only)")
+        if args.cpu_seconds > 0 else None,
     }
 
 
