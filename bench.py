@@ -354,6 +354,7 @@ def main():
         "acceptance": tot["accepts"] / tot["trials"],
         "depletants_per_move": tot["depletants_drawn"] / tot["trials"],
         "resolved_per_move": tot["depletants_resolved"] / tot["trials"],
+        "pair_tests_per_s": tot["overlap_checks"] / dt,
         "roofline": _roofline("sphere", profiled and region == hp.V0_BALL, per_launch_checks, per_launch_moves,
                               avg_phase_s, "phase_sphere_kernel (one launch per checkerboard colour)",
                               extra={"frac_minimal": achieved_minimal / VALU_PEAK_LANE_OPS,
@@ -498,6 +499,9 @@ def _line(metric_value, tot, dt, steps, warmup, workload, extra):
         "depletant_checks_per_s": tot["depletants_resolved"] / dt,
         "acceptance": tot["accepts"] / max(tot["trials"], 1),
     }
+    if "overlap_checks" in tot:
+        # colloid pair tests executed (spheres: every stencil entry; convex shapes: the narrow phase)
+        d["pair_tests_per_s"] = tot["overlap_checks"] / dt
     d.update(extra)
     return d
 
