@@ -134,6 +134,7 @@ int derive(hpmc_sim* s)
     int n = static_cast<int>(floor(s->L / wmin));
     if (n % 2) n -= 1;
     if (n < 2) return fail(s, HPMC_EBOX, "box smaller than two cells of width 2 R_circ + d_dep");
+    // (this also keeps every cell coordinate below 1024: the sphere kernel packs them in 10 bits)
     if (static_cast<int64_t>(n) * n * n > 0x3FFFFFFF) return fail(s, HPMC_EBOX, "too many cells");
     s->n = n;
     s->w = s->L / static_cast<double>(n);

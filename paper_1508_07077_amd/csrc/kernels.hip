@@ -130,6 +130,8 @@ __device__ inline int lane_id() { return __lane_id(); }
 
 // periodic wrap of a cell coordinate that is at most one cell outside [0, n)
 __device__ inline int wrap1(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
+// cell id of packed coordinates cx | cy << 10 | cz << 20 (at most 1024 cells per axis)
+__device__ inline int cell_id(const Params& P, int X) { return (X & 1023) + P.n * (((X >> 10) & 1023) + P.n * (X >> 20)); }
 
 // this lane's offset in the de-duplicated cell stencil: 27 lanes over
 // {0, -1, +1}^3 (n > 2) or 8 lanes over {0, +1}^3 (n = 2); lane 0 is the cell
@@ -1226,7 +1228,7 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const WorkG& 
     const Mat3 Rnone{};
 
     // the chunk: lane k < P.chunk holds active cell gw * P.chunk + k
-    int Ck = -1, startk = 0, nck = 0;
+    int Xk = 0, startk = 0, nck = 0;  // Xk: the cell's coordinates, cx | cy << 10 | cz << 20
     {
         int a = gw * P.chunk + lane;
         if (lane < P.chunk && a < P.active_cells) {
@@ -1234,7 +1236,8 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const WorkG& 
             const int cxk = 2 * ax + (colour & 1);
             const int cyk = 2 * ay + ((colour >> 1) & 1);
             const int czk = 2 * az + ((colour >> 2) & 1);
-            Ck = cxk + P.n * (cyk + P.n * czk);
+            Xk = cxk | (cyk << 10) | (czk << 20);
+            const int Ck = cxk + P.n * (cyk + P.n * czk);
             startk = W.cell_start[Ck];
             nck = W.cell_start[Ck + 1] - startk;
         }
@@ -1262,7 +1265,7 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const WorkG& 
         int k = 0;
         for (int kk = 1; kk < P.chunk; ++kk)
             if (static_cast<int>(rdlane_u(static_cast<uint32_t>(offk), kk)) <= sl) k = kk;
-        const int o = __shfl(offk, k, 64), nk = __shfl(nck, k, 64), Cs = __shfl(Ck, k, 64);
+        const int o = __shfl(offk, k, 64), nk = __shfl(nck, k, 64), Cs = cell_id(P, __shfl(Xk, k, 64));
         const bool valid = tl < T && sl < nslots;
         const uint32_t purpose = q == 0 ? kSelect : (q == 1 ? kTrans : (q == 2 ? kAccept : kPoisson));
         const uint32_t index = q >= 3 ? static_cast<uint32_t>(q - 3) : 0u;
@@ -1278,10 +1281,8 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const WorkG& 
             stencil_ranges(P, W, nb, -1, 0, 0, 0, es, ec);
             return;
         }
-        // the cell's coordinates from its id (wave-uniform arithmetic, no registers held per lane)
-        const int C = static_cast<int>(rdlane_u(static_cast<uint32_t>(Ck), k));
-        const int cyz = C / P.n;
-        stencil_ranges(P, W, nb, C, C - P.n * cyz, cyz % P.n, cyz / P.n, es, ec);
+        const int X = static_cast<int>(rdlane_u(static_cast<uint32_t>(Xk), k));
+        stencil_ranges(P, W, nb, cell_id(P, X), X & 1023, (X >> 10) & 1023, X >> 20, es, ec);
     };
     // pipeline: ranges two cells ahead, records one cell ahead
     auto next_cell = [&](unsigned long long& m) -> int {
@@ -1303,7 +1304,7 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const WorkG& 
         __builtin_amdgcn_s_waitcnt(0);
         wave_sync();
         const SphereStage S0 = stage_buf(buf);
-        const int C = static_cast<int>(rdlane_u(static_cast<uint32_t>(Ck), kc));
+        const int C = cell_id(P, static_cast<int>(rdlane_u(static_cast<uint32_t>(Xk), kc)));
         const int start = static_cast<int>(rdlane_u(static_cast<uint32_t>(startk), kc));
         const int nc = static_cast<int>(rdlane_u(static_cast<uint32_t>(nck), kc));
         const int nst = nst_cur;
