@@ -107,6 +107,21 @@ def test_box_too_small(hp):
     L.hpmc_destroy(h)
 
 
+def test_cell_grid_cap(hp):
+    """at most 2^30 - 1 cells: 1022 per axis is the largest grid (every cell
+    coordinate below 1024, which the sphere kernel packs in 10 bits); 1024 is refused"""
+    L = hp.lib()
+    h = _handle(hp, L=1022.5)  # unit spheres, no depletants: cells of width >= 1
+    assert L.hpmc_set_shape(h, 0, _dp([1.0]), 1) == 0
+    ws = ctypes.c_size_t()
+    assert L.hpmc_workspace_bytes(h, ctypes.byref(ws)) == 0
+    assert ws.value >= 1022 ** 3 * 4  # the cell counts alone
+    L.hpmc_destroy(h)
+    h = _handle(hp, L=1024.5)
+    assert L.hpmc_set_shape(h, 0, _dp([1.0]), 1) == -2
+    L.hpmc_destroy(h)
+
+
 def test_workspace_grows_with_trace(hp):
     L = hp.lib()
     h = _handle(hp)
