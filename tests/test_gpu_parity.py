@@ -212,6 +212,39 @@ def test_empty_and_zero_inputs():
     assert e.value.code == -1
 
 
+def test_sparse_box_of_514_cells_per_axis():
+    """a box of 514 cells per axis (136 M cells, 1,500 unit spheres): cell
+    coordinates 512 and 513 take the top bits of the kernel's packed per-lane
+    coordinates; a 2 x 2 x 2 cluster in the far corner keeps neighbours,
+    depletants and CB trials there; every trial record and the end state
+    equal the oracle's"""
+    import types
+
+    from scipy.spatial import cKDTree
+
+    L = 514 * 1.1 + 0.05  # d_dep 0.1: cells of width >= 1.1, 514 of them per side
+    n = 1500
+    rng = np.random.default_rng(51)
+    pos = rng.uniform(0.0, L, size=(n, 3))
+    while True:
+        bad = {j for _, j in cKDTree(pos, boxsize=L).query_pairs(1.0)}
+        if not bad:
+            break
+        for j in bad:
+            pos[j] = rng.uniform(0.0, L, 3)
+    pos[:8] = [[L - 0.55 - 1.05 * a, L - 0.55 - 1.05 * b, L - 0.55 - 1.05 * c]
+               for a in (0, 1) for b in (0, 1) for c in (0, 1)]
+    assert not cKDTree(pos, boxsize=L).query_pairs(1.0)
+    sp = types.SimpleNamespace(n=n, L=L, seed=7, replica_id=0, kind=wl.SPHERE, params=(1.0,), z_p=15.0, d_dep=0.1,
+                               n_trial=1, d_trans=0.3, a_rot=0.0, p_rot=0.0)
+    g, o = make_pair(sp, np.ascontiguousarray(pos.T))
+    assert g.n_axis == 514
+    tot, div = compare_sweeps(g, o, 1)
+    assert div == 0 and tot["trials"] == n and tot["accepts"] > 0 and tot["cb_trials"] > 0
+    hi = np.floor(pos / (L / 514)).max(axis=0)
+    assert (hi >= 512).all()
+
+
 def test_full_size_c3_sampled_cells():
     """N = 1,048,576 spheres at the benchmark's settings: one traced GPU sweep
     from the generator's lattice; for sampled cells (one per phase) the oracle
