@@ -275,8 +275,8 @@ int hpmc_batch_workspace_bytes(int n_sims, size_t* bytes);
  * ECAPACITY).  Each handle keeps its own state, workspace and random streams,
  * so every replica's trajectory is identical to what hpmc_sweep gives it
  * alone.  All handles must be ready
- * (shape, workspace, state) and use the stream of sims[0]; tracing must be
- * off.  batch_ws: device scratch of hpmc_batch_workspace_bytes(n_sims); the
+ * (shape, workspace, state) and use the stream of sims[0] (EINVAL
+ * otherwise); tracing must be off.  batch_ws: device scratch of hpmc_batch_workspace_bytes(n_sims); the
  * descriptors are copied into it on the stream from pinned host staging
  * buffers of sims[0], so the call does not wait for the device unless out is
  * given.  out: NULL or n_sims counter records (synchronises); their

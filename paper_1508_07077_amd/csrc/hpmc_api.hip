@@ -1213,6 +1213,10 @@ int hpmc_sweep_batch(hpmc_sim* const* sims, int n_sims, void* batch_ws, size_t b
     for (int i = 0; i < n_sims; ++i) {
         if (!sims[i]) return HPMC_EINVAL;
         int r = check_ready(sims[i], true, &par[static_cast<size_t>(i)]);
+        // a member's own uploads (its table, below) go on its stream: the batch
+        // runs on the first member's, so one stream for all keeps them ordered
+        if (r == HPMC_OK && sims[i]->stream != sims[0]->stream)
+            r = fail(sims[0], HPMC_EINVAL, "every handle of a batch must use the stream of the first");
         if (r == HPMC_OK) r = upload_table(sims[i]);
         if (r != HPMC_OK) return r;
         if (sims[i]->trace) return fail(sims[i], HPMC_EINVAL, "tracing is per handle; disable it for batched sweeps");
@@ -1354,6 +1358,9 @@ int hpmc_autotune_batch(hpmc_sim* const* sims, int n_sims, void* batch_ws, size_
         Params Px;
         int r = check_ready(x, true, &Px);
         if (r != HPMC_OK) return r;
+        // the copies below and the synchronisation at the end use this stream,
+        // and each group's sweeps that of its first member
+        if (x->stream != s0->stream) return fail(s0, HPMC_EINVAL, "every handle of a batch must use the stream of the first");
         if (x->trace) return fail(x, HPMC_EINVAL, "tracing is per handle; disable it for batched sweeps");
         cl[static_cast<size_t>(i)] = batch_class(x, Px);
         off[static_cast<size_t>(i)] = need;

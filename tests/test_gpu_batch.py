@@ -61,6 +61,33 @@ def test_batch_equals_alone(kind):
             assert np.array_equal(qa, qb)
 
 
+def test_batch_needs_one_stream():
+    """handles on different streams are not batched: both batched entry points
+    refuse them before any device work, and every handle still sweeps alone"""
+    import torch
+
+    import paper_1508_07077_amd as hp
+
+    sps = _replicas(wl.SPHERE, 2, 5)
+    side = torch.cuda.Stream()
+    sims = []
+    for i, sp in enumerate(sps):
+        g = hp.Sim(sp.n, sp.L, sp.seed, sp.replica_id, stream=side if i == 1 else None)
+        g.set_shape(sp.kind, sp.params)
+        g.set_fugacity(sp.z_p, sp.d_dep, sp.n_trial)
+        g.set_moves(sp.d_trans, sp.a_rot, sp.p_rot)
+        g.set_state(*sp.initial_state())
+        sims.append(g)
+    b = hp.Batch(sims)
+    for call in (lambda: b.sweep(1), lambda: b.autotune(1)):
+        with pytest.raises(hp.HpmcError) as e:
+            call()
+        assert e.value.code == -1 and "stream" in str(e.value)
+    for g, sp in zip(sims, sps):
+        assert g.get_state()[2] == 0
+        assert g.sweep(1)["trials"] == sp.n
+
+
 def test_batch_matches_oracle():
     import paper_1508_07077_amd as hp
     from oracle import pyoracle
