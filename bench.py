@@ -59,19 +59,19 @@ def shell_ops_per_check(R0: float, r_i: float) -> float:
 # busy with active lanes (rocprofv3 VALUBusy x VALUUtilization).  The HBM bytes
 # per launch are FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the factors a plain
 # 256 MiB device copy reads off the same counters).
-PROFILED_KERNEL_DIGEST = "596f4ede8bd24a09"
+PROFILED_KERNEL_DIGEST = "115c5d2513932231"
 PROFILE = {
     # 1,048,576 spheres, ball region, 212.05 resolved checks per move
-    "sphere": {"a_dep": 174.89, "b_move": 15152.8, "valu_instr_per_move": 1212.7, "valu_busy": 77.61,
-               "valu_utilization": 67.31, "traffic_bytes_per_launch": 65229907},
+    "sphere": {"a_dep": 174.89, "b_move": 15152.8, "valu_instr_per_move": 1212.7, "valu_busy": 78.10,
+               "valu_utilization": 67.31, "traffic_bytes_per_launch": 65233511},
     # 16,384 hemispheres at eta_r 0.4, 72.31 resolved checks per move
-    "hemisphere": {"a_dep": 393.58, "b_move": 34067.5, "valu_instr_per_move": 2099.3, "valu_busy": 12.64,
-                   "valu_utilization": 46.54, "traffic_bytes_per_launch": 4406101},
+    "hemisphere": {"a_dep": 393.58, "b_move": 34067.5, "valu_instr_per_move": 2099.3, "valu_busy": 12.54,
+                   "valu_utilization": 46.54, "traffic_bytes_per_launch": 4406106},
     # 256 swept-disk replicas, both launch groups of a phase, 56.50 resolved checks per move
     "discoid": {"a_dep": 480.09, "b_move": 29100.9, "valu_instr_per_move": 2306.1,
-                "valu_busy": {"replicas of two cells per axis": 0.83, "the others": 43.51},
+                "valu_busy": {"replicas of two cells per axis": 0.82, "the others": 43.57},
                 "valu_utilization": {"replicas of two cells per axis": 35.06, "the others": 38.14},
-                "traffic_bytes_per_phase": 85917741},
+                "traffic_bytes_per_phase": 85918366},
 }
 
 

@@ -1198,8 +1198,25 @@ __device__ inline void load_table(const WorkG& W, LAS unsigned char* smem)
     for (int i = threadIdx.x; i < kGuide; i += blockDim.x) sG[i] = gG[i];
 }
 
+// a wave's LDS counters added to one of the HBM counter copies (lane 0)
+__device__ inline void flush_wave_counters(const WorkG& W, LAS unsigned long long* wcnt, int gw)
+{
+    wave_sync();
+    if (lane_id() == 0) {
+        GAS unsigned long long* dst = W.counters + static_cast<size_t>(gw % kCounterCopies) * kCounterStride;
+#pragma unroll
+        for (int k = 0; k < kNumCounters; ++k) {
+            const unsigned long long v = wcnt[k];
+            if (v) __hip_atomic_fetch_add(dst + k, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
 // One wave's share of a phase: the chunk gw of active cells (P.chunk cells).
-template <bool F32, bool SHELL>
+// OWN_COUNTERS: the wave's LDS counters start at zero here and go to HBM at
+// the end; otherwise the caller clears and flushes them (a launch of many
+// phases keeps adding to them).
+template <bool F32, bool SHELL, bool OWN_COUNTERS = true>
 __device__ __forceinline__ void phase_sphere_body(const Params& P, const WorkG& W, int phase, int gw)
 {
     LAS unsigned char* smem = lds_base();
@@ -1220,7 +1237,7 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const WorkG& 
     auto wadd = [&](int k, unsigned long long v) {
         __hip_atomic_fetch_add(wcnt + k, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     };
-    if (lane < kNumCounters) wcnt[lane] = 0ull;
+    if (OWN_COUNTERS && lane < kNumCounters) wcnt[lane] = 0ull;
     unsigned fallbacks = 0;  // FP64 fallbacks of the guarded FP32 tests (this lane)
 
     const int colour = W.perm[phase];
@@ -1534,15 +1551,7 @@ __device__ __forceinline__ void phase_sphere_body(const Params& P, const WorkG& 
         const int fb = wave_sum(static_cast<int>(fallbacks));
         if (lane == 0 && fb) wadd(cFp64Fallbacks, static_cast<unsigned long long>(fb));
     }
-    wave_sync();
-    if (lane == 0) {
-        GAS unsigned long long* dst = W.counters + static_cast<size_t>(gw % kCounterCopies) * kCounterStride;
-#pragma unroll
-        for (int k = 0; k < kNumCounters; ++k) {
-            const unsigned long long v = wcnt[k];
-            if (v) __hip_atomic_fetch_add(dst + k, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
+    if constexpr (OWN_COUNTERS) flush_wave_counters(W, wcnt, gw);
 }
 
 #ifndef HPMC_SPHERE_WAVES_PER_EU
@@ -1620,6 +1629,10 @@ __global__ __launch_bounds__(64 * kSmallWaves) void sweep_small_kernel(const Des
     P.chunk = (P.active_cells + kSmallWaves - 1) / kSmallWaves;
     if (P.chunk > 64) P.chunk = 64;
     load_table(WG, lds_base());
+    // each wave's LDS counters add up over every phase and sweep of the launch
+    LAS unsigned long long* wcnt =
+        (LAS unsigned long long*)(lds_base() + kTableLds + static_cast<size_t>(wv) * P.wave_lds + P.off_cnt);
+    if (lane_id() < kNumCounters) wcnt[lane_id()] = 0ull;
     for (int sw = 0; sw < n_sweeps; ++sw) {
         P.sweep = sweep0 + static_cast<uint32_t>(sw);
         if (tid == 0) grid_setup(P, W);
@@ -1671,7 +1684,7 @@ __global__ __launch_bounds__(64 * kSmallWaves) void sweep_small_kernel(const Des
         __syncthreads();
         for (int phase = 0; phase < 8; ++phase) {
             for (int gw = wv; gw * P.chunk < P.active_cells; gw += kSmallWaves)
-                phase_sphere_body<F32, SHELL>(P, WG, phase, gw);
+                phase_sphere_body<F32, SHELL, false>(P, WG, phase, gw);
             __syncthreads();
         }
         for (int q = tid; q < P.N; q += nt) {
@@ -1683,6 +1696,7 @@ __global__ __launch_bounds__(64 * kSmallWaves) void sweep_small_kernel(const Des
         }
         __syncthreads();
     }
+    flush_wave_counters(WG, wcnt, wv);
     if (tid == 0) *W.sweep_dev = sweep0 + static_cast<uint32_t>(n_sweeps);
 }
 
