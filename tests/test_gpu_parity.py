@@ -212,6 +212,27 @@ def test_empty_and_zero_inputs():
     assert e.value.code == -1
 
 
+@pytest.mark.parametrize("n_trial,precision", [(0, 0), (4, 0), (4, 1)])
+def test_multi_sweep_call_totals_match_the_oracle(n_trial, precision):
+    """25 sweeps in one launch of the small-box kernel (a batched call with
+    counters; every wave adds to its counters over all phases and sweeps of
+    the launch and flushes once) report the oracle's totals of the decision
+    counters, and end in its state"""
+    import paper_1508_07077_amd as hp
+
+    sp = wl.c1_spheres_small(n_trial)
+    pos, _ = sp.initial_state()
+    g, o = make_pair(sp, pos, trace=False, precision=precision)
+    cg, co = hp.Batch([g]).sweep(25)[0], o.sweep(25)
+    for k in ("trials", "accepts", "rej_cell_exit", "rej_overlap", "rej_depletant", "rej_cb_zero",
+              "rej_cb_metropolis", "depletants_drawn", "depletants_resolved", "cb_trials"):
+        assert cg[k] == co[k], k
+    assert cg["trials"] == 25 * sp.n and cg["accepts"] > 0
+    pg, _, sg = g.get_state()
+    po, _, so = o.get_state()
+    assert sg == so == 25 and np.array_equal(pg, po)
+
+
 def test_sparse_box_of_514_cells_per_axis():
     """a box of 514 cells per axis (136 M cells, 1,500 unit spheres): cell
     coordinates 512 and 513 take the top bits of the kernel's packed per-lane
